@@ -116,7 +116,7 @@ class Discretisation:
     """One p-Laplacian discretisation: mesh, tables, operators."""
 
     def __init__(self, nx, ny, nz, k, nq, p, eps, vertices=None, rho=None,
-                 f=None, load=None, chunk=4096):
+                 f=None, load=None, chunk=4096, compute_load=True):
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.k, self.nq = int(k), int(nq)
         self.p, self.eps = float(p), float(eps)
@@ -175,10 +175,13 @@ class Discretisation:
 
         self.rho = (np.ones(self.E) if rho is None
                     else np.asarray(rho, dtype=np.float64).copy())
+        self.f = f
         if load is not None:
             self.b = np.asarray(load, dtype=np.float64).copy()
-        else:
+        elif compute_load:
             self.b = self.load_vector(f)
+        else:
+            self.b = None   # large meshes: load entries computed where sampled
 
     # ------------------------------------------------------------------
     def with_(self, **kw) -> "Discretisation":
@@ -297,10 +300,10 @@ class Discretisation:
                             * energy_density(g, self.p, self.eps))
         return total - np.dot(self.b, self.mask * u)
 
-    def load_vector(self, f=None):
+    def load_vector(self, f=None, elems=None):
         """b_i = sum_e sum_q w detJ f(x_q) phi_i(x_q); f = 1 by default."""
         out = np.zeros(self.N)
-        for ch in self._chunks(np.arange(self.E)):
+        for ch in self._chunks(self._all(elems)):
             _, detJ, _, xq = self.geometry(ch)
             fq = np.ones_like(detJ) if f is None else f(xq[..., 0], xq[..., 1], xq[..., 2])
             out += self.assemble((self.w[None, :] * detJ * fq) @ self.Bval, ch)
@@ -344,7 +347,10 @@ class Discretisation:
 
     def residual_at(self, u, dofs):
         """R(u) at the listed DOFs only (same arithmetic as ``residual``)."""
-        return self.residual(u, self.elements_touching(dofs))[np.asarray(dofs)]
+        dofs = np.asarray(dofs)
+        elems = self.elements_touching(dofs)
+        b = self.b if self.b is not None else self.load_vector(self.f, elems)
+        return (self.mask * (self.apply_unmasked(u, elems) - b))[dofs]
 
     def jvp_at(self, u, v, dofs):
         return self.jvp(u, v, self.elements_touching(dofs))[np.asarray(dofs)]

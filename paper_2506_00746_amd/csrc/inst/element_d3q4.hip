@@ -1,0 +1,6 @@
+// Element kernel instantiation for D1 = 3 nodes and NQ = 4 Gauss points per direction.
+#include "../element_kernel.hpp"
+
+namespace feod {
+FEOD_INSTANTIATE(3, 4)
+}  // namespace feod

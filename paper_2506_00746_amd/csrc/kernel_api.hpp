@@ -1,0 +1,80 @@
+// Host-visible launch interface between the C ABI layer and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace feod {
+
+// Exponent r = (p-2)/2 of the flux coefficient a^r, specialised by sqrt chains.
+enum PowKind : int { POW_ZERO = 0, POW_QUARTER = 1, POW_HALF = 2, POW_ONE = 3, POW_GENERIC = 4 };
+
+enum : int { OP_RESIDUAL = 0, OP_JVP = 1, OP_RESJVP = 2, OP_ENERGY = 3, OP_GRAD = 4, OP_DIAG = 5, OP_COUNT = 6 };
+
+// Arguments of the fused element kernel (passed by value).
+struct ElemParams {
+  const double* u;        // L-vector (FP64)
+  const double* v;        // second L-vector: JVP direction or adjoint lambda
+  const int32_t* emap;    // E x Ne element-to-DOF map, -1 on Dirichlet DOFs
+  const double* rho;      // E coefficients or nullptr (all ones)
+  const double* verts;    // (nx+1)(ny+1)(nz+1) x 3, curved meshes only
+  const void* tab;        // 1D tables in the kernel precision: B, D (nq x D1), w, xi (nq)
+  void* out0;             // E-vector (kernel precision) or E doubles (energy, gradient)
+  void* out1;             // second E-vector (residual + JVP)
+  int32_t E, nx, ny, nz;
+  double h[3];            // affine element sizes
+  double p, eps2, r, inv_p;
+  int32_t powkind;
+};
+
+using ElemLaunch = hipError_t (*)(const ElemParams&, hipStream_t);
+
+struct ElemLaunchers {
+  int D1, NQ;
+  struct PerPrec {
+    ElemLaunch op[OP_COUNT][2];  // [op][curved]
+  } prec[2];                     // [0] FP64, [1] FP32
+  int eb[2];
+};
+
+// Registered (D1, NQ) instantiations; returns nullptr when not built.
+const ElemLaunchers* find_launchers(int D1, int NQ);
+
+// ---- L-vector kernels (vector_kernels.hip) ----------------------------------
+constexpr int kRedBlocks = 1024;  // fixed grid of the two-stage reductions
+
+// y[i] = sum_{j in row i} Y[idx[j]] - bm[i] (bm may be nullptr); optional
+// second E-vector / output pair for residual + JVP.  TE = double or float.
+hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y0, const void* Y1,
+                           bool fp32, const double* bm, double* out0, double* out1, int64_t n,
+                           hipStream_t s);
+
+// partial[b] = sum over block b's grid-stride share of x[i]*y[i] (y == nullptr: x[i]).
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* partial,
+                              hipStream_t s);
+// out[0] = sum_b partial[b] * sign + (add ? add[0] : 0), fixed order, one block.
+hipError_t launch_reduce_final(const double* partial, int nparts, double* out, double sign,
+                               const double* add, hipStream_t s);
+
+// CG steps on device-resident scalars (sc = scalar array):
+//   alpha = sc[i_rz] / sc[i_pq]; x += alpha p; r -= alpha q; z = r * dinv (if dinv);
+//   partial0 = r.z (or r.r), partial1 = r.r (if dinv).
+hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* q,
+                            const double* dinv, const double* sc, int i_rz, int i_pq, int64_t n,
+                            double* partial0, double* partial1, hipStream_t s);
+//   beta = sc[i_new] / sc[i_old]; p = z + beta p
+hipError_t launch_cg_xpay(double* p, const double* z, const double* sc, int i_new, int i_old,
+                          int64_t n, hipStream_t s);
+// y = a*x + b*y with host scalars; x or y may alias out
+hipError_t launch_axpby(double* out, double a, const double* x, double b, const double* y,
+                        int64_t n, hipStream_t s);
+// out = mask-free copy / fill
+hipError_t launch_fill(double* out, double val, int64_t n, hipStream_t s);
+// dinv[i] = d[i] > 0 ? 1/d[i] : 0
+hipError_t launch_invert_diag(double* dinv, const double* d, int64_t n, hipStream_t s);
+// out[i] = in[i] * (emask[i]) where mask derived from toff rows (interior iff row non-empty)
+hipError_t launch_mask_copy(double* out, const double* in, const int32_t* toff, int64_t n,
+                            hipStream_t s);
+// checks: flag[0] = 1 if any x[i] non-finite (writes only on failure)
+hipError_t launch_copy_scalar(double* dst, const double* src, int count, hipStream_t s);
+
+}  // namespace feod

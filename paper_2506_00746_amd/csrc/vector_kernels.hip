@@ -1,0 +1,222 @@
+// L-vector kernels: the deterministic transposed-map gather G^T, two-stage
+// fixed-order FP64 reductions, and fused CG vector updates with the CG
+// scalars kept on the device.
+#include <hip/hip_runtime.h>
+
+#include "kernel_api.hpp"
+
+namespace feod {
+
+constexpr int kVecThreads = 256;
+
+static inline int vec_blocks(int64_t n) {
+  int64_t b = (n + kVecThreads - 1) / kVecThreads;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// G^T: each DOF sums the E-vector entries listed in its row, in ascending
+// E-vector order (no atomics: bitwise reproducible).  Dirichlet rows are
+// empty and their load entry is 0, so the output row is exactly 0.
+template <class TE, bool TWO>
+__global__ __launch_bounds__(kVecThreads) void gather_t_kernel(const int32_t* __restrict__ off,
+                                                               const int32_t* __restrict__ idx,
+                                                               const TE* __restrict__ Y0,
+                                                               const TE* __restrict__ Y1,
+                                                               const double* __restrict__ bm,
+                                                               double* __restrict__ out0,
+                                                               double* __restrict__ out1, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i >= n) return;
+  const int j0 = off[i], j1 = off[i + 1];
+  double s0 = 0, s1 = 0;
+  for (int j = j0; j < j1; ++j) {
+    const int t = idx[j];
+    s0 += (double)Y0[t];
+    if (TWO) s1 += (double)Y1[t];
+  }
+  if (bm != nullptr) s0 -= bm[i];
+  out0[i] = s0;
+  if (TWO) out1[i] = s1;
+}
+
+hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y0, const void* Y1,
+                           bool fp32, const double* bm, double* out0, double* out1, int64_t n,
+                           hipStream_t s) {
+  const int nb = vec_blocks(n);
+  if (fp32) {
+    if (Y1)
+      hipLaunchKernelGGL((gather_t_kernel<float, true>), dim3(nb), dim3(kVecThreads), 0, s, off, idx,
+                         (const float*)Y0, (const float*)Y1, bm, out0, out1, n);
+    else
+      hipLaunchKernelGGL((gather_t_kernel<float, false>), dim3(nb), dim3(kVecThreads), 0, s, off, idx,
+                         (const float*)Y0, nullptr, bm, out0, nullptr, n);
+  } else {
+    if (Y1)
+      hipLaunchKernelGGL((gather_t_kernel<double, true>), dim3(nb), dim3(kVecThreads), 0, s, off, idx,
+                         (const double*)Y0, (const double*)Y1, bm, out0, out1, n);
+    else
+      hipLaunchKernelGGL((gather_t_kernel<double, false>), dim3(nb), dim3(kVecThreads), 0, s, off, idx,
+                         (const double*)Y0, nullptr, bm, out0, nullptr, n);
+  }
+  return hipGetLastError();
+}
+
+// Fixed-shape block reduction: wavefront shuffles, then the 4 wave sums in order.
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double ws[kVecThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < kVecThreads / 64; ++i) s += ws[i];
+  }
+  return s;  // valid in thread 0
+}
+
+__global__ __launch_bounds__(kVecThreads) void dot_partial_kernel(const double* __restrict__ x,
+                                                                  const double* __restrict__ y,
+                                                                  int64_t n, double* __restrict__ partial) {
+  double s = 0;
+  const int64_t stride = (int64_t)kRedBlocks * kVecThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride)
+    s += y ? x[i] * y[i] : x[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* partial,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(dot_partial_kernel, dim3(kRedBlocks), dim3(kVecThreads), 0, s, x, y, n, partial);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void reduce_final_kernel(const double* __restrict__ partial,
+                                                                   int nparts, double* out, double sign,
+                                                                   const double* add) {
+  double s = 0;
+  for (int i = threadIdx.x; i < nparts; i += kVecThreads) s += partial[i];
+  s = block_sum(s);
+  if (threadIdx.x == 0) out[0] = sign * s + (add ? add[0] : 0.0);
+}
+
+hipError_t launch_reduce_final(const double* partial, int nparts, double* out, double sign,
+                               const double* add, hipStream_t s) {
+  hipLaunchKernelGGL(reduce_final_kernel, dim3(1), dim3(kVecThreads), 0, s, partial, nparts, out, sign, add);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                                double* __restrict__ z,
+                                                                const double* __restrict__ p,
+                                                                const double* __restrict__ q,
+                                                                const double* __restrict__ dinv,
+                                                                const double* __restrict__ sc, int i_rz,
+                                                                int i_pq, int64_t n, double* partial0,
+                                                                double* partial1) {
+  const double alpha = sc[i_rz] / sc[i_pq];
+  double s0 = 0, s1 = 0;
+  const int64_t stride = (int64_t)kRedBlocks * kVecThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
+    x[i] += alpha * p[i];
+    const double ri = r[i] - alpha * q[i];
+    r[i] = ri;
+    if (dinv) {
+      const double zi = ri * dinv[i];
+      z[i] = zi;
+      s0 += ri * zi;
+      s1 += ri * ri;
+    } else {
+      s0 += ri * ri;
+    }
+  }
+  s0 = block_sum(s0);
+  if (threadIdx.x == 0) partial0[blockIdx.x] = s0;
+  if (dinv) {
+    __syncthreads();
+    s1 = block_sum(s1);
+    if (threadIdx.x == 0) partial1[blockIdx.x] = s1;
+  }
+}
+
+hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* q,
+                            const double* dinv, const double* sc, int i_rz, int i_pq, int64_t n,
+                            double* partial0, double* partial1, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(kRedBlocks), dim3(kVecThreads), 0, s, x, r, z, p, q, dinv, sc,
+                     i_rz, i_pq, n, partial0, partial1);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void cg_xpay_kernel(double* __restrict__ p, const double* __restrict__ z,
+                                                              const double* __restrict__ sc, int i_new,
+                                                              int i_old, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i >= n) return;
+  const double beta = sc[i_new] / sc[i_old];
+  p[i] = z[i] + beta * p[i];
+}
+
+hipError_t launch_cg_xpay(double* p, const double* z, const double* sc, int i_new, int i_old, int64_t n,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(cg_xpay_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, p, z, sc, i_new, i_old, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void axpby_kernel(double* out, double a, const double* x, double b,
+                                                            const double* y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i >= n) return;
+  out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+
+hipError_t launch_axpby(double* out, double a, const double* x, double b, const double* y, int64_t n,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(axpby_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, out, a, x, b, y, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void fill_kernel(double* out, double val, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i < n) out[i] = val;
+}
+
+hipError_t launch_fill(double* out, double val, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, out, val, n);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kVecThreads) void invert_diag_kernel(double* dinv, const double* d, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i < n) dinv[i] = d[i] > 0.0 ? 1.0 / d[i] : 0.0;
+}
+
+hipError_t launch_invert_diag(double* dinv, const double* d, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(invert_diag_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, dinv, d, n);
+  return hipGetLastError();
+}
+
+// interior iff the DOF's transposed-map row is non-empty
+__global__ __launch_bounds__(kVecThreads) void mask_copy_kernel(double* out, const double* in,
+                                                                const int32_t* toff, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  if (i < n) out[i] = (toff[i + 1] > toff[i]) ? in[i] : 0.0;
+}
+
+hipError_t launch_mask_copy(double* out, const double* in, const int32_t* toff, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(mask_copy_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, out, in, toff, n);
+  return hipGetLastError();
+}
+
+__global__ void copy_scalar_kernel(double* dst, const double* src, int count) {
+  if ((int)threadIdx.x < count) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+hipError_t launch_copy_scalar(double* dst, const double* src, int count, hipStream_t s) {
+  hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+
+}  // namespace feod

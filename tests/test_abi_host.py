@@ -1,0 +1,105 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared
+symbol, and its host-side setup (1D tables, maps, load vector, validation)
+agrees with the independent oracle."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import paper_2506_00746_amd as feod
+from oracle import Discretisation
+from workloads import Workload, make_inputs
+
+
+def test_library_exports_every_declared_symbol():
+    L = feod.lib()
+    names = feod.header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    for n in ("feod_setup_mesh", "feod_residual", "feod_jacobian_apply", "feod_newton_solve",
+              "feod_adjoint_gradient"):
+        assert n in names
+
+
+@pytest.mark.parametrize("k,nq", [(1, 2), (2, 3), (2, 4), (3, 5), (4, 6), (7, 9)])
+def test_tables_match_oracle(k, nq):
+    if k == 2 and nq == 4:
+        pytest.skip("pair not built")
+    h = feod.HostSetup(1, 1, 1, k, nq)
+    d = Discretisation(1, 1, 1, k, nq, 3.0, 1e-2)
+    assert np.abs(h.nodes - d.nodes1d).max() < 1e-15
+    assert np.abs(h.qpts - d.qp1d).max() < 1e-15
+    assert np.abs(h.qwts - d.qw1d).max() < 1e-15
+    assert np.abs(h.B - d.L1).max() < 1e-14
+    assert np.abs(h.D - d.dL1).max() < 1e-12 * max(1, np.abs(d.dL1).max())
+
+
+@pytest.mark.parametrize("shape,k,nq", [((2, 3, 4), 2, 3), ((3, 2, 2), 3, 5), ((1, 1, 1), 1, 2),
+                                        ((4, 4, 4), 2, 3)])
+def test_maps_match_oracle(shape, k, nq):
+    h = feod.HostSetup(*shape, k, nq)
+    d = Discretisation(*shape, k, nq, 3.0, 1e-2)
+    expect = np.where(d.mask[d.elem_dofs] > 0, d.elem_dofs, -1)
+    assert np.array_equal(h.emap, expect)
+    # transposed map: row i lists the E-vector positions of DOF i, ascending
+    flat = expect.ravel()
+    for i in range(d.N):
+        row = h.tidx[h.toff[i]:h.toff[i + 1]]
+        assert np.array_equal(row, np.nonzero(flat == i)[0])
+
+
+@pytest.mark.parametrize("perturb", [False, True])
+def test_load_matches_oracle(perturb):
+    w = Workload("t", 3, 2, 4, 2, 3, 3.0, 1e-2, 5, perturb=perturb)
+    inp = make_inputs(w)
+    h = feod.HostSetup(3, 2, 4, 2, 3, vertices=inp["vertices"])
+    d = Discretisation(3, 2, 4, 2, 3, 3.0, 1e-2, vertices=inp["vertices"])
+    assert np.abs(h.load - d.b).max() < 1e-15 * 100
+
+
+def test_setup_rejects_bad_input():
+    def setup(**kw):
+        args = dict(nx=2, ny=2, nz=2, order_k=2, nq=3, p=3.0, eps=1e-2, vertices=None,
+                    rho=None, load=None, stream=None)
+        args.update(kw)
+        d = feod.feod.MeshDesc(*[args[f] for f, _ in feod.feod.MeshDesc._fields_])
+        ctx = ctypes.c_void_p()
+        st = feod.lib().feod_setup_mesh(ctypes.byref(d), ctypes.byref(ctx))
+        if st == 0:
+            feod.lib().feod_destroy(ctx)
+        return st, feod.lib().feod_last_error(None).decode()
+    assert setup()[0] == 0
+    assert setup(nx=0)[0] == feod.feod.FEOD_EINVAL
+    assert setup(p=1.0)[0] == feod.feod.FEOD_EINVAL
+    assert setup(p=float("nan"))[0] == feod.feod.FEOD_EINVAL
+    assert setup(eps=-1.0)[0] == feod.feod.FEOD_EINVAL
+    assert setup(eps=0.0, p=1.5)[0] == feod.feod.FEOD_EINVAL
+    st, msg = setup(order_k=6, nq=2)
+    assert st == feod.feod.FEOD_EUNSUPPORTED and "k=6" in msg
+    # inverted element
+    w = Workload("t", 2, 2, 2, 2, 3, 3.0, 1e-2, 5, perturb=True)
+    v = make_inputs(w)["vertices"].copy()
+    v[13] = [0.9, 0.9, 0.9]  # centre vertex pulled across its neighbours
+    st, msg = setup(vertices=v.ctypes.data)
+    assert st == feod.feod.FEOD_EINVAL and "detJ" in msg
+
+
+def test_unbound_context_and_null_args():
+    L = feod.lib()
+    d = feod.feod.MeshDesc(2, 2, 2, 2, 3, 3.0, 1e-2, None, None, None, None)
+    ctx = ctypes.c_void_p()
+    assert L.feod_setup_mesh(ctypes.byref(d), ctypes.byref(ctx)) == 0
+    try:
+        assert L.feod_residual(ctx, 8, 16, 0) == feod.feod.FEOD_ESTATE
+        nb = ctypes.c_size_t()
+        assert L.feod_workspace_bytes(ctx, ctypes.byref(nb)) == 0 and nb.value > 0
+        assert L.feod_bind_workspace(ctx, None, nb.value) == feod.feod.FEOD_EINVAL
+        assert L.feod_bind_workspace(ctx, 256, 16) == feod.feod.FEOD_EINVAL  # too small
+        b = ctypes.c_double()
+        f = ctypes.c_double()
+        assert L.feod_kernel_cost(ctx, 1, 0, ctypes.byref(b), ctypes.byref(f)) == 0
+        assert b.value > 0 and f.value > 0
+    finally:
+        L.feod_destroy(ctx)
+    assert L.feod_destroy(None) == 0

@@ -1,0 +1,135 @@
+"""GPU (HIP) vs oracle parity of the operator applies, element by element.
+
+Small meshes: whole vectors, relative L2 <= 1e-12 in FP64 (every mesh spans
+several workgroup batches with a ragged last batch).  Full workload sizes:
+whole-vector GPU applies checked at sampled DOFs the oracle computes one by
+one, plus properties that hold at any size.
+"""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_helpers import announce, dev, host, relerr, setup
+from workloads import WORKLOADS, Workload, make_inputs
+
+pytestmark = pytest.mark.gpu
+
+SMALL = [
+    Workload("c1", 4, 4, 4, 2, 3, 3.0, 1e-2, 1),
+    Workload("q2-ragged-rho", 5, 3, 7, 2, 3, 3.0, 1e-2, 21, rho=True),
+    Workload("q2-curved", 3, 4, 2, 2, 3, 2.5, 1e-2, 22, perturb=True, rho=True),
+    Workload("q3-p4", 3, 5, 2, 3, 5, 4.0, 1e-3, 23),
+    Workload("q3-curved", 2, 3, 3, 3, 5, 4.0, 1e-3, 24, perturb=True),
+    Workload("q4-p2.5", 3, 2, 3, 4, 6, 2.5, 1e-2, 25),
+    Workload("q7-curved", 2, 2, 3, 7, 9, 3.0, 1e-2, 26, perturb=True),
+    Workload("q1-curved", 5, 4, 3, 1, 2, 2.5, 1e-2, 27, perturb=True, rho=True),
+    Workload("q2-nq4-generic-p", 3, 3, 4, 2, 4, 1.5, 0.1, 28, perturb=True),
+    Workload("q2-p2", 4, 3, 2, 2, 3, 2.0, 1e-2, 29),
+]
+IDS = [w.name for w in SMALL]
+
+
+@pytest.mark.parametrize("w", SMALL, ids=IDS)
+def test_residual_jvp_energy_fp64(w):
+    announce("parity fp64", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    r = host(prob.residual(u))
+    jv = host(prob.jacobian_apply(u, v))
+    r2, jv2 = prob.residual_and_jvp(u, v)
+    e = host(prob.energy(u))[0]
+    r_o, jv_o = ora.residual(inp["u"]), ora.jvp(inp["u"], inp["v"])
+    assert relerr(r, r_o) <= 1e-12
+    assert relerr(jv, jv_o) <= 1e-12
+    assert relerr(host(r2), r_o) <= 1e-12
+    assert relerr(host(jv2), jv_o) <= 1e-12
+    e_o = ora.energy(inp["u"])
+    assert abs(e - e_o) <= 1e-12 * abs(e_o)
+    inner = ora.mask > 0
+    assert np.all(r[~inner] == 0) and np.all(jv[~inner] == 0)
+
+
+@pytest.mark.parametrize("w", SMALL, ids=IDS)
+def test_grad_rho_kernel_fp64(w):
+    announce("grad kernel fp64", w)
+    prob, ora, inp = setup(w)
+    lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, ora.N)
+    g = host(prob.grad_rho(dev(inp["u"]), dev(lam)))
+    assert relerr(g, ora.grad_rho(inp["u"], lam)) <= 1e-12
+
+
+@pytest.mark.parametrize("w", SMALL, ids=IDS)
+def test_mixed_precision_error_vs_fp64_oracle(w):
+    announce("parity mixed", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    r = host(prob.residual(u, prec="mixed"))
+    jv = host(prob.jacobian_apply(u, v, prec="mixed"))
+    e_r = relerr(r, ora.residual(inp["u"]))
+    e_j = relerr(jv, ora.jvp(inp["u"], inp["v"]))
+    lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, ora.N)
+    e_g = relerr(host(prob.grad_rho(u, dev(lam), prec="mixed")), ora.grad_rho(inp["u"], lam))
+    print(f"mixed-precision rel. L2 error vs FP64 oracle [{w.name}]: residual {e_r:.2e} "
+          f"jvp {e_j:.2e} grad {e_g:.2e}")
+    assert e_r < 1e-4 and e_j < 1e-4 and e_g < 1e-4
+
+
+def test_bitwise_determinism_and_symmetry():
+    w = SMALL[2]
+    announce("determinism", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    wv = dev(np.random.default_rng(3).uniform(-1, 1, ora.N))
+    a = host(prob.jacobian_apply(u, v))
+    b = host(prob.jacobian_apply(u, v))
+    assert np.array_equal(a, b)
+    assert np.array_equal(host(prob.residual(u)), host(prob.residual(u)))
+    lhs = float(host(wv) @ a)
+    rhs = float(host(v) @ host(prob.jacobian_apply(u, wv)))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_aliasing_and_bad_arguments_rejected():
+    import paper_2506_00746_amd as feod
+    w = SMALL[0]
+    announce("errors", w)
+    prob, _, inp = setup(w, oracle=False)
+    u = dev(inp["u"])
+    with pytest.raises(feod.FeodError, match="EINVAL"):
+        prob.residual(u, out=u)
+    with pytest.raises(feod.FeodError, match="EINVAL"):
+        prob.jacobian_apply(u, u, out=u)
+    with pytest.raises(ValueError):
+        prob.residual(u[:-1])
+    with pytest.raises(TypeError):
+        prob.residual(u.float())
+
+
+def _sample_dofs(ora, n=160, seed=0):
+    rng = np.random.default_rng(seed)
+    inner = np.nonzero(ora.mask)[0]
+    pick = rng.choice(inner, n, replace=False)
+    corners = [inner[0], inner[-1], inner[len(inner) // 2], 0, ora.N - 1]
+    return np.unique(np.concatenate([pick, corners]))
+
+
+@pytest.mark.parametrize("name", ["c2", "c3", "c4", "c5"])
+def test_full_size_sampled_parity(name):
+    w = WORKLOADS[name]
+    announce("full-size sampled parity", name)
+    prob, ora, inp = setup(w, compute_load=False)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    dofs = _sample_dofs(ora)
+    r = host(prob.residual(u))
+    jv = host(prob.jacobian_apply(u, v))
+    assert relerr(r[dofs], ora.residual_at(inp["u"], dofs)) <= 1e-12
+    assert relerr(jv[dofs], ora.jvp_at(inp["u"], inp["v"], dofs)) <= 1e-12
+    # properties at full size: Dirichlet rows exactly zero, bitwise repeatable
+    inner = ora.mask > 0
+    assert np.all(r[~inner] == 0) and np.all(jv[~inner] == 0)
+    assert np.array_equal(jv, host(prob.jacobian_apply(u, v)))
+    rm = host(prob.jacobian_apply(u, v, prec="mixed"))
+    print(f"[{name}] mixed JVP rel. error at sampled DOFs: "
+          f"{relerr(rm[dofs], jv[dofs]):.2e}")
+    del prob
+    torch.cuda.empty_cache()

@@ -1,0 +1,82 @@
+"""GPU Newton-CG and adjoint solves vs the oracle's direct-solve versions,
+and the autograd design gradient vs central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import paper_2506_00746_amd as feod
+from oracle import Discretisation, adjoint, newton
+from tests.gpu_helpers import announce, dev, host, relerr, setup
+from workloads import WORKLOADS, Workload, make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_newton_c1_matches_oracle(prec):
+    w = WORKLOADS["c1"]
+    announce("newton c1", prec)
+    prob, ora, _ = setup(w)
+    u, rep = prob.newton_solve(rtol=1e-12, prec=prec)
+    u_o, info = newton(ora, tol=1e-13)
+    print("GPU report", rep, "oracle iters", info["iters"])
+    assert rep["status"] == 0
+    assert rep["res_final"] <= 1e-12 * rep["ref_norm"]
+    assert relerr(host(u), u_o) <= 1e-10
+    # certified by the oracle residual at the GPU solution
+    assert np.linalg.norm(ora.residual(host(u))) <= 1e-10 * np.linalg.norm(ora.mask * ora.b)
+
+
+def test_newton_curved_q3_matches_oracle():
+    w = Workload("nc", 3, 2, 3, 3, 5, 3.0, 1e-2, 31, perturb=True, rho=True)
+    announce("newton curved", w)
+    prob, ora, _ = setup(w)
+    u, rep = prob.newton_solve(rtol=1e-12)
+    u_o, _ = newton(ora, tol=1e-13)
+    assert relerr(host(u), u_o) <= 1e-10
+
+
+def test_adjoint_matches_oracle():
+    w = Workload("adj", 4, 3, 3, 2, 3, 3.0, 1e-2, 32, perturb=True, rho=True)
+    announce("adjoint", w)
+    prob, ora, inp = setup(w)
+    u, _ = prob.newton_solve(rtol=1e-13)
+    b = dev(ora.b)
+    for prec in ("fp64", "mixed"):
+        grad, lam, rep = prob.adjoint_gradient(u, b, rtol=1e-13, prec=prec)
+        lam_o, grad_o = adjoint(ora, host(u), ora.b)
+        print(prec, rep, relerr(host(grad), grad_o))
+        assert relerr(host(lam), lam_o) <= 1e-10
+        assert relerr(host(grad), grad_o) <= 1e-10
+
+
+def test_design_solve_autograd_vs_finite_differences_c4():
+    w = WORKLOADS["c4"]
+    announce("design autograd c4")
+    inp = make_inputs(w)
+    prob = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, rho=inp["rho"], device="cuda:0")
+    b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load, device="cuda:0")
+    rho = torch.as_tensor(inp["rho"], device="cuda:0").requires_grad_(True)
+    opts = {"rtol": 1e-13}
+    u = feod.DesignSolve.apply(rho, prob, opts)
+    phi = torch.dot(b, u)
+    phi.backward()
+    grad = rho.grad.detach().cpu().numpy()
+    u0 = u.detach()
+
+    def phi_at(r):
+        prob.set_rho(r)
+        us, _ = prob.newton_solve(u0, init_poisson=0, rtol=1e-13)
+        return float(torch.dot(b, us))
+
+    rho0 = torch.as_tensor(inp["rho"], device="cuda:0")
+    worst = 0.0
+    for e in inp["fd_elems"]:
+        h = 1e-3 * float(rho0[e])
+        rp, rm = rho0.clone(), rho0.clone()
+        rp[e] += h
+        rm[e] -= h
+        fd = (phi_at(rp) - phi_at(rm)) / (2 * h)
+        worst = max(worst, abs(fd - grad[e]) / abs(grad[e]))
+    print("worst relative FD mismatch over 20 elements:", worst)
+    assert worst <= 1e-5
