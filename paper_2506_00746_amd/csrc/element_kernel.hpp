@@ -1,18 +1,24 @@
 // Fused element kernel of the finite element operator decomposition
-// A = G^T B^T D B G (paper, Fig. 1, Eq. (1)-(2)), one workgroup per batch of
-// EB elements:
+// A = G^T B^T D B G (paper, Fig. 1, Eq. (1)-(2)).  One workgroup processes a
+// batch of EB elements in five phases separated by barriers; in every phase a
+// thread owns whole 1D lines, so each value it loads feeds D1 or NQ
+// multiply-adds whose table operand is uniform across the wavefront (the 1D
+// tables travel in the kernel arguments and are read as scalars):
 //
-//   G    gather of M u (and M v) through the element-to-DOF map into LDS
-//        (Dirichlet DOFs are encoded as -1 in the map and read as 0);
-//   B    reference gradients at the nq^3 Gauss points by three sum-factorised
-//        1D passes (x, y, z) through LDS;
-//   D    the pointwise flux at every quadrature point, on dual numbers for the
-//        Jacobian action (Eq. (2)), with the trilinear geometry recomputed per
-//        point on curved meshes;
-//   B^T  three transposed passes (z, y, x) back to element DOFs, written as
-//        the output E-vector (G^T is a separate deterministic gather).
-//
-// Quadrature-point data lives only in LDS and registers.
+//   A  G + x-pass   line (c,b): gather the D1 DOFs of an x-line of M u (and
+//                   M v) through the element-to-DOF map straight from HBM,
+//                   contract with B and D in x -> LDS.
+//   B  y-pass       line (c,qx): contract in y -> LDS (three partial fields).
+//   C  z-pass, D, z-back   line (qx,qy): finish the reference gradients at the
+//                   NQ points of the z-column in registers, apply the pointwise
+//                   operator D there (dual numbers for the Jacobian action,
+//                   trilinear geometry recomputed per point on curved meshes),
+//                   and contract the fluxes back over z -> LDS.  Quadrature
+//                   data never leaves registers.
+//   D  y-back       line (c,qx) -> LDS.
+//   E  x-back       line (c,b): D1 element residual entries written
+//                   contiguously to the output E-vector in HBM (G^T is the
+//                   separate deterministic gather).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -22,169 +28,33 @@
 
 namespace feod {
 
-constexpr int kThreads = 256;
-
-template <int D1, int NQ>
-struct Shape {
-  static constexpr int Ne = D1 * D1 * D1;
-  static constexpr int NQ3 = NQ * NQ * NQ;
-  static constexpr int NX = D1 * D1 * NQ;   // one x-pass output field
-  static constexpr int NY = D1 * NQ * NQ;   // one y-pass output field
-  // per-element LDS footprint in scalars: two input fields, x/y scratch, two
-  // gradient fields, 8 vertices
-  static constexpr int per_elem = 2 * Ne + 2 * NX + 3 * NY + 6 * NQ3 + 24;
-};
-
+// 1D tables by value in the kernel arguments: B[q*D1+a] = l_a(x_q),
+// D[q*D1+a] = l_a'(x_q), Gauss weights w and points xi on [0,1].
 template <int D1, int NQ, class T>
-struct Batch {
-  static constexpr int lds_target = 48 * 1024;
-  static constexpr int raw = lds_target / (Shape<D1, NQ>::per_elem * (int)sizeof(T));
-  static constexpr int EB = raw < 1 ? 1 : (raw > 16 ? 16 : raw);
+struct Tab {
+  T B[NQ * D1];
+  T D[NQ * D1];
+  T w[NQ];
+  T xi[NQ];
 };
 
-// ---------------------------------------------------------------------------
-// B: in[el][c][b][a] (D1^3) -> G[el][d][qz][qy][qx] (3 fields of NQ^3),
-// d = 0,1,2 the x,y,z reference derivative.
-template <int D1, int NQ, int EB, class T>
-__device__ __forceinline__ void grad_forward(const T* __restrict__ sB, const T* __restrict__ sD,
-                                             const T* in, T* X, T* Y, T* G) {
-  using S = Shape<D1, NQ>;
-  const int tid = threadIdx.x;
-  // x-pass: X0[c][b][qx] = sum_a B[qx][a] in[c][b][a], X1 with D
-  for (int i = tid; i < EB * S::NX; i += kThreads) {
-    const int el = i / S::NX, rem = i - el * S::NX;
-    const int qx = rem % NQ, cb = rem / NQ;
-    const T* src = in + el * S::Ne + cb * D1;
-    T s0 = 0, s1 = 0;
-#pragma unroll
-    for (int a = 0; a < D1; ++a) {
-      const T x = src[a];
-      s0 += sB[qx * D1 + a] * x;
-      s1 += sD[qx * D1 + a] * x;
-    }
-    X[el * 2 * S::NX + rem] = s0;
-    X[el * 2 * S::NX + S::NX + rem] = s1;
-  }
-  __syncthreads();
-  // y-pass: Y0 = D_y X0 (-> d/dy), Y1 = B_y X0 (-> d/dz), Y2 = B_y X1 (-> d/dx)
-  for (int i = tid; i < EB * S::NY; i += kThreads) {
-    const int el = i / S::NY, rem = i - el * S::NY;
-    const int qx = rem % NQ, qy = (rem / NQ) % NQ, c = rem / (NQ * NQ);
-    const T* x0 = X + el * 2 * S::NX + c * D1 * NQ + qx;
-    const T* x1 = x0 + S::NX;
-    T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-    for (int b = 0; b < D1; ++b) {
-      const T b0 = x0[b * NQ], b1 = x1[b * NQ];
-      s0 += sD[qy * D1 + b] * b0;
-      s1 += sB[qy * D1 + b] * b0;
-      s2 += sB[qy * D1 + b] * b1;
-    }
-    T* y = Y + el * 3 * S::NY + rem;
-    y[0] = s0;
-    y[S::NY] = s1;
-    y[2 * S::NY] = s2;
-  }
-  __syncthreads();
-  // z-pass: Gx = B_z Y2, Gy = B_z Y0, Gz = D_z Y1
-  for (int i = tid; i < EB * S::NQ3; i += kThreads) {
-    const int el = i / S::NQ3, q = i - el * S::NQ3;
-    const int qxy = q % (NQ * NQ), qz = q / (NQ * NQ);
-    const T* y = Y + el * 3 * S::NY + qxy;
-    T gx = 0, gy = 0, gz = 0;
-#pragma unroll
-    for (int c = 0; c < D1; ++c) {
-      const T bz = sB[qz * D1 + c];
-      gx += bz * y[2 * S::NY + c * NQ * NQ];
-      gy += bz * y[c * NQ * NQ];
-      gz += sD[qz * D1 + c] * y[S::NY + c * NQ * NQ];
-    }
-    T* g = G + el * 3 * S::NQ3 + q;
-    g[0] = gx;
-    g[S::NQ3] = gy;
-    g[2 * S::NQ3] = gz;
-  }
-  __syncthreads();
-}
+// Launch shape per (D1, NQ, precision): threads per workgroup and elements
+// per batch, chosen so that phase C (NQ^2 lines per element) fills the
+// workgroup and the LDS footprint leaves room for several workgroups per CU.
+template <int D1, int NQ, class T>
+struct Config {
+  static constexpr int lines_c = NQ * NQ;
+  static constexpr int NT = lines_c <= 16 ? 64 : 128;
+  static constexpr int EB0 = NT / lines_c;
+  static constexpr int EB = EB0 < 1 ? 1 : EB0;
+};
 
-// B^T: G[el][d][q] -> out (E-vector of the batch, T), out[el*Ne + (c*D1+b)*D1+a]
-template <int D1, int NQ, int EB, class T>
-__device__ __forceinline__ void grad_backward(const T* __restrict__ sB, const T* __restrict__ sD,
-                                              const T* G, T* X, T* Y, T* __restrict__ out,
-                                              int n_valid) {
-  using S = Shape<D1, NQ>;
-  const int tid = threadIdx.x;
-  // z-back: Y0[c][qy][qx] = sum_qz B[qz][c] Gx, Y1 = B Gy, Y2 = D Gz
-  for (int i = tid; i < EB * S::NY; i += kThreads) {
-    const int el = i / S::NY, rem = i - el * S::NY;
-    const int qxy = rem % (NQ * NQ), c = rem / (NQ * NQ);
-    const T* g = G + el * 3 * S::NQ3 + qxy;
-    T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-    for (int qz = 0; qz < NQ; ++qz) {
-      const T bz = sB[qz * D1 + c];
-      s0 += bz * g[qz * NQ * NQ];
-      s1 += bz * g[S::NQ3 + qz * NQ * NQ];
-      s2 += sD[qz * D1 + c] * g[2 * S::NQ3 + qz * NQ * NQ];
-    }
-    T* y = Y + el * 3 * S::NY + rem;
-    y[0] = s0;
-    y[S::NY] = s1;
-    y[2 * S::NY] = s2;
-  }
-  __syncthreads();
-  // y-back: X0[c][b][qx] = sum_qy B[qy][b] Y0 ; X1 = sum_qy D[qy][b] Y1 + B[qy][b] Y2
-  for (int i = tid; i < EB * S::NX; i += kThreads) {
-    const int el = i / S::NX, rem = i - el * S::NX;
-    const int qx = rem % NQ, b = (rem / NQ) % D1, c = rem / (NQ * D1);
-    const T* y = Y + el * 3 * S::NY + c * NQ * NQ + qx;
-    T s0 = 0, s1 = 0;
-#pragma unroll
-    for (int qy = 0; qy < NQ; ++qy) {
-      const T by = sB[qy * D1 + b];
-      s0 += by * y[qy * NQ];
-      s1 += sD[qy * D1 + b] * y[S::NY + qy * NQ] + by * y[2 * S::NY + qy * NQ];
-    }
-    X[el * 2 * S::NX + rem] = s0;
-    X[el * 2 * S::NX + S::NX + rem] = s1;
-  }
-  __syncthreads();
-  // x-back: out[c][b][a] = sum_qx D[qx][a] X0 + B[qx][a] X1
-  for (int i = tid; i < n_valid * S::Ne; i += kThreads) {
-    const int el = i / S::Ne, rem = i - el * S::Ne;
-    const int a = rem % D1, cb = rem / D1;
-    const T* x = X + el * 2 * S::NX + cb * NQ;
-    T s = 0;
-#pragma unroll
-    for (int qx = 0; qx < NQ; ++qx) s += sD[qx * D1 + a] * x[qx] + sB[qx * D1 + a] * x[S::NX + qx];
-    out[i] = s;
-  }
-}
-
-// Geometry at one quadrature point: adjugate (transposed cofactor) of the
-// Jacobian Jg = dx/dxi and its determinant.  Jg^{-1} = adj / det.
-template <class T>
-__device__ __forceinline__ void trilinear_adj(const T* X, T xi, T et, T ze, T adj[3][3], T* det) {
-  const T mx = T(1) - xi, me = T(1) - et, mz = T(1) - ze;
-  T J[3][3];
-#pragma unroll
-  for (int al = 0; al < 3; ++al) {
-    const T* x = X + al;  // X[v*3 + al], v = i + 2j + 4l
-    J[al][0] = (me * mz) * (x[3] - x[0]) + (et * mz) * (x[9] - x[6]) + (me * ze) * (x[15] - x[12]) + (et * ze) * (x[21] - x[18]);
-    J[al][1] = (mx * mz) * (x[6] - x[0]) + (xi * mz) * (x[9] - x[3]) + (mx * ze) * (x[18] - x[12]) + (xi * ze) * (x[21] - x[15]);
-    J[al][2] = (mx * me) * (x[12] - x[0]) + (xi * me) * (x[15] - x[3]) + (mx * et) * (x[18] - x[6]) + (xi * et) * (x[21] - x[9]);
-  }
-  adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-  adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-  adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-  adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-  adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-  adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-  adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-  adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-  adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-  *det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-}
+template <int D1, int NQ, int F>
+struct Lds {
+  static constexpr int X = 2 * NQ * D1 * D1;  // one field of x-pass output
+  static constexpr int Y = 3 * NQ * NQ * D1;  // one field of y-pass output
+  static constexpr int per_elem = F * X + 2 * Y + 24;
+};
 
 // Deterministic sum of n LDS values by one wavefront (fixed order).
 template <class T>
@@ -197,48 +67,25 @@ __device__ __forceinline__ double wave_sum(const T* vals, int n, int lane) {
 }
 
 template <int D1, int NQ, class T, int OP, bool CURVED>
-__global__ __launch_bounds__(kThreads) void element_kernel(ElemParams P) {
-  using S = Shape<D1, NQ>;
-  constexpr int EB = Batch<D1, NQ, T>::EB;
-  constexpr bool two_fields = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD);
-  __shared__ T sB[NQ * D1], sD[NQ * D1], sW[NQ], sQ[NQ];
-  __shared__ T smem[EB * S::per_elem];
-  T* sU = smem;                       // EB * Ne
-  T* sV = sU + EB * S::Ne;            // EB * Ne
-  T* X = sV + EB * S::Ne;             // EB * 2 * NX
-  T* Y = X + EB * 2 * S::NX;          // EB * 3 * NY
-  T* G1 = Y + EB * 3 * S::NY;         // EB * 3 * NQ3
-  T* G2 = G1 + EB * 3 * S::NQ3;       // EB * 3 * NQ3
-  T* sX = G2 + EB * 3 * S::NQ3;       // EB * 24
+__global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
+  constexpr int NT = Config<D1, NQ, T>::NT;
+  constexpr int EB = Config<D1, NQ, T>::EB;
+  constexpr int Ne = D1 * D1 * D1;
+  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD) ? 2 : 1;  // input fields
+  constexpr int O = (OP == OP_RESJVP) ? 2 : 1;                                    // output fields
+  constexpr bool REDUCE = (OP == OP_ENERGY || OP == OP_GRAD);
+  using L = Lds<D1, NQ, F>;
+  __shared__ T smem[EB * L::per_elem];
+  T* Xs = smem;                       // [el][f][2][c][b][qx]
+  T* Ys = Xs + EB * F * L::X;         // [el][f][3][c][qy][qx], reused for H and K
+  T* Vs = Ys + EB * 2 * L::Y;         // [el][24] vertex coordinates
 
   const int tid = threadIdx.x;
   const int e0 = blockIdx.x * EB;
   const int n_valid = min(EB, P.E - e0);
-  const T* tab = static_cast<const T*>(P.tab);
-  for (int i = tid; i < NQ * D1; i += kThreads) {
-    sB[i] = tab[i];
-    sD[i] = tab[NQ * D1 + i];
-  }
-  for (int i = tid; i < NQ; i += kThreads) {
-    sW[i] = tab[2 * NQ * D1 + i];
-    sQ[i] = tab[2 * NQ * D1 + NQ + i];
-  }
-  // G: gather through the map (-1 = Dirichlet DOF, read as 0)
-  for (int i = tid; i < EB * S::Ne; i += kThreads) {
-    const int el = i / S::Ne;
-    T xu = 0, xv = 0;
-    if (el < n_valid) {
-      const int m = P.emap[(int64_t)e0 * S::Ne + i];
-      if (m >= 0) {
-        xu = (T)P.u[m];
-        if (two_fields) xv = (T)P.v[m];
-      }
-    }
-    sU[i] = xu;
-    if (two_fields) sV[i] = xv;
-  }
+
   if (CURVED) {
-    for (int i = tid; i < EB * 24; i += kThreads) {
+    for (int i = tid; i < EB * 24; i += NT) {
       const int el = i / 24, r = i - el * 24, vtx = r / 3, al = r - vtx * 3;
       T val = 0;
       if (el < n_valid) {
@@ -247,137 +94,348 @@ __global__ __launch_bounds__(kThreads) void element_kernel(ElemParams P) {
         const int gi = (ex + (vtx & 1)) + (P.nx + 1) * ((ey + ((vtx >> 1) & 1)) + (P.ny + 1) * (ez + (vtx >> 2)));
         val = (T)P.verts[(int64_t)gi * 3 + al];
       }
-      sX[i] = val;
+      Vs[i] = val;
+    }
+  }
+
+  // ---- A: gather + x-pass ---------------------------------------------------
+  for (int l = tid; l < EB * D1 * D1; l += NT) {
+    const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
+    T in[F][D1];
+    if (el < n_valid) {
+      const int32_t* m = P.emap + (int64_t)(e0 + el) * Ne + cb * D1;
+#pragma unroll
+      for (int a = 0; a < D1; ++a) {
+        const int idx = m[a];
+        in[0][a] = idx >= 0 ? (T)P.u[idx] : T(0);
+        if (F == 2) in[F - 1][a] = idx >= 0 ? (T)P.v[idx] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+#pragma unroll
+        for (int a = 0; a < D1; ++a) in[f][a] = 0;
+    }
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      T* x = Xs + (el * F + f) * L::X + cb * NQ;
+#pragma unroll
+      for (int qx = 0; qx < NQ; ++qx) {
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int a = 0; a < D1; ++a) {
+          s0 += tb.B[qx * D1 + a] * in[f][a];
+          s1 += tb.D[qx * D1 + a] * in[f][a];
+        }
+        x[qx] = s0;
+        x[NQ * D1 * D1 + qx] = s1;
+      }
     }
   }
   __syncthreads();
 
-  grad_forward<D1, NQ, EB, T>(sB, sD, sU, X, Y, G1);
-  if (two_fields) grad_forward<D1, NQ, EB, T>(sB, sD, sV, X, Y, G2);
+  // ---- B: y-pass: Y0 = D_y X0 (d/dy), Y1 = B_y X0 (d/dz), Y2 = B_y X1 (d/dx) --
+  for (int l = tid; l < EB * D1 * NQ; l += NT) {
+    const int el = l / (D1 * NQ), rem = l - el * (D1 * NQ);
+    const int c = rem / NQ, qx = rem - c * NQ;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const T* x = Xs + (el * F + f) * L::X + c * D1 * NQ + qx;
+      T x0[D1], x1[D1];
+#pragma unroll
+      for (int b = 0; b < D1; ++b) {
+        x0[b] = x[b * NQ];
+        x1[b] = x[NQ * D1 * D1 + b * NQ];
+      }
+      T* y = Ys + (el * 2 + f) * L::Y + c * NQ * NQ + qx;
+#pragma unroll
+      for (int qy = 0; qy < NQ; ++qy) {
+        T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int b = 0; b < D1; ++b) {
+          s0 += tb.D[qy * D1 + b] * x0[b];
+          s1 += tb.B[qy * D1 + b] * x0[b];
+          s2 += tb.B[qy * D1 + b] * x1[b];
+        }
+        y[qy * NQ] = s0;
+        y[NQ * NQ * D1 + qy * NQ] = s1;
+        y[2 * NQ * NQ * D1 + qy * NQ] = s2;
+      }
+    }
+  }
+  __syncthreads();
 
-  // D at every quadrature point of the batch
+  // ---- C: z-pass, pointwise D, z-back (registers) ---------------------------
+  T* red = Xs;  // per-line partial sums for energy / gradient
   const T eps2 = (T)P.eps2, r = (T)P.r, inv_p = (T)P.inv_p;
   const int kind = P.powkind;
-  for (int i = tid; i < EB * S::NQ3; i += kThreads) {
-    const int el = i / S::NQ3, q = i - el * S::NQ3;
-    const int qx = q % NQ, qy = (q / NQ) % NQ, qz = q / (NQ * NQ);
-    const T w = sW[qx] * sW[qy] * sW[qz];
-    T adj[3][3], det;
-    if (CURVED) {
-      trilinear_adj<T>(sX + el * 24, sQ[qx], sQ[qy], sQ[qz], adj, &det);
-    } else {
-      const T hx = (T)P.h[0], hy = (T)P.h[1], hz = (T)P.h[2];
-      det = hx * hy * hz;
+  for (int l = tid; l < EB * NQ * NQ; l += NT) {
+    const int el = l / (NQ * NQ), qxy = l - el * (NQ * NQ);
+    const int qy = qxy / NQ, qx = qxy - qy * NQ;
+    T g[F][3][NQ];
 #pragma unroll
-      for (int a = 0; a < 3; ++a)
+    for (int f = 0; f < F; ++f)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) adj[a][b] = 0;
-      adj[0][0] = hy * hz;
-      adj[1][1] = hx * hz;
-      adj[2][2] = hx * hy;
-    }
-    const T inv_det = T(1) / det;
-    T* g1 = G1 + el * 3 * S::NQ3 + q;
-    T* g2 = G2 + el * 3 * S::NQ3 + q;
-    const T rg[3] = {g1[0], g1[S::NQ3], g1[2 * S::NQ3]};
-    // physical gradient g = Jg^{-T} ghat = adj^T ghat / det
-    T gu[3];
+      for (int d = 0; d < 3; ++d)
 #pragma unroll
-    for (int a = 0; a < 3; ++a) gu[a] = (adj[0][a] * rg[0] + adj[1][a] * rg[1] + adj[2][a] * rg[2]) * inv_det;
-    const int e = e0 + el;
-    const T rho = (P.rho != nullptr && el < n_valid) ? (T)P.rho[e] : T(1);
-    if (OP == OP_RESIDUAL) {
-      T F[3];
-      flux<T, T>(gu, eps2, r, kind, F);
-      const T s = rho * w;  // Fhat = rho w det Jg^{-1} F = rho w adj F
+        for (int q = 0; q < NQ; ++q) g[f][d][q] = 0;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) g1[a * S::NQ3] = s * (adj[a][0] * F[0] + adj[a][1] * F[1] + adj[a][2] * F[2]);
-    } else if (OP == OP_JVP || OP == OP_RESJVP) {
-      const T rv[3] = {g2[0], g2[S::NQ3], g2[2 * S::NQ3]};
-      dual<T> g[3], F[3];
+    for (int c = 0; c < D1; ++c) {
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        g[a].v = gu[a];
-        g[a].d = (adj[0][a] * rv[0] + adj[1][a] * rv[1] + adj[2][a] * rv[2]) * inv_det;
-      }
-      flux<dual<T>, T>(g, eps2, r, kind, F);
-      const T s = rho * w;
+      for (int f = 0; f < F; ++f) {
+        const T* y = Ys + (el * 2 + f) * L::Y + c * NQ * NQ + qxy;
+        const T y0 = y[0], y1 = y[NQ * NQ * D1], y2 = y[2 * NQ * NQ * D1];
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const T fd = s * (adj[a][0] * F[0].d + adj[a][1] * F[1].d + adj[a][2] * F[2].d);
-        if (OP == OP_RESJVP) {
-          g1[a * S::NQ3] = s * (adj[a][0] * F[0].v + adj[a][1] * F[1].v + adj[a][2] * F[2].v);
-          g2[a * S::NQ3] = fd;
-        } else {
-          g1[a * S::NQ3] = fd;
+        for (int qz = 0; qz < NQ; ++qz) {
+          g[f][0][qz] += tb.B[qz * D1 + c] * y2;
+          g[f][1][qz] += tb.B[qz * D1 + c] * y0;
+          g[f][2][qz] += tb.D[qz * D1 + c] * y1;
         }
       }
-    } else if (OP == OP_ENERGY) {
-      T W, c;
-      density<T>(gu, eps2, r, kind, inv_p, &W, &c);
-      g1[0] = rho * w * det * W;
-    } else if (OP == OP_GRAD) {
-      const T rv[3] = {g2[0], g2[S::NQ3], g2[2 * S::NQ3]};
-      T gl[3];
+    }
+    const bool valid = el < n_valid;
+    const T rho = (P.rho != nullptr && valid) ? (T)P.rho[e0 + el] : T(1);
+    const T wxy = tb.w[qx] * tb.w[qy] * rho;
+    // geometry: affine -> constant diagonal; curved -> Jg = J0 + xi_z * J1
+    T J0[3][3], J1[3][2];
+    if (CURVED) {
+      const T* X = Vs + el * 24;
+      const T xi = tb.xi[qx], et = tb.xi[qy], mx = T(1) - xi, me = T(1) - et;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) gl[a] = (adj[0][a] * rv[0] + adj[1][a] * rv[1] + adj[2][a] * rv[2]) * inv_det;
-      T W, c;
-      density<T>(gu, eps2, r, kind, inv_p, &W, &c);
-      g1[0] = -w * det * c * (gu[0] * gl[0] + gu[1] * gl[1] + gu[2] * gl[2]);
+      for (int al = 0; al < 3; ++al) {
+        const T* x = X + al;  // x[3v] = coordinate al of vertex v = i + 2j + 4l
+        const T a0 = me * (x[3] - x[0]) + et * (x[9] - x[6]);
+        const T a1 = me * (x[15] - x[12]) + et * (x[21] - x[18]);
+        const T b0 = mx * (x[6] - x[0]) + xi * (x[9] - x[3]);
+        const T b1 = mx * (x[18] - x[12]) + xi * (x[21] - x[15]);
+        J0[al][0] = a0;
+        J1[al][0] = a1 - a0;
+        J0[al][1] = b0;
+        J1[al][1] = b1 - b0;
+        J0[al][2] = (mx * me) * (x[12] - x[0]) + (xi * me) * (x[15] - x[3]) + (mx * et) * (x[18] - x[6]) +
+                    (xi * et) * (x[21] - x[9]);
+      }
+    }
+    const T hinv[3] = {(T)P.hinv[0], (T)P.hinv[1], (T)P.hinv[2]};
+    const T sdet[3] = {(T)P.sdet[0], (T)P.sdet[1], (T)P.sdet[2]};  // det * hinv (affine)
+    const T det_aff = (T)P.det;
+    double part = 0;  // energy / gradient partial over the column
+#pragma unroll
+    for (int qz = 0; qz < NQ; ++qz) {
+      const T wq = wxy * tb.w[qz];
+      T gu[3], gv[3];
+      T adj[3][3], inv_det = T(1), det = det_aff;
+      if (CURVED) {
+        const T ze = tb.xi[qz];
+        T J[3][3];
+#pragma unroll
+        for (int al = 0; al < 3; ++al) {
+          J[al][0] = J0[al][0] + ze * J1[al][0];
+          J[al][1] = J0[al][1] + ze * J1[al][1];
+          J[al][2] = J0[al][2];
+        }
+        adj[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+        adj[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+        adj[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+        adj[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+        adj[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+        adj[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+        adj[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+        adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+        adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+        det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
+        inv_det = T(1) / det;
+        // physical gradient g = Jg^{-T} ghat = adj^T ghat / det
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gu[a] = (adj[0][a] * g[0][0][qz] + adj[1][a] * g[0][1][qz] + adj[2][a] * g[0][2][qz]) * inv_det;
+          if (F == 2) gv[a] = (adj[0][a] * g[F - 1][0][qz] + adj[1][a] * g[F - 1][1][qz] + adj[2][a] * g[F - 1][2][qz]) * inv_det;
+        }
+      } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          gu[a] = g[0][a][qz] * hinv[a];
+          if (F == 2) gv[a] = g[F - 1][a][qz] * hinv[a];
+        }
+      }
+      // reference flux Fhat = rho w det Jg^{-1} F = rho w adj F
+      T Fo[O][3];
+      if (OP == OP_RESIDUAL) {
+        flux<T, T>(gu, eps2, r, kind, Fo[0]);
+      } else if (OP == OP_JVP || OP == OP_RESJVP) {
+        dual<T> gd[3], Fd[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gd[a] = {gu[a], gv[a]};
+        flux<dual<T>, T>(gd, eps2, r, kind, Fd);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          Fo[0][a] = Fd[a].d;
+          if (O == 2) Fo[O - 1][a] = Fd[a].v;  // residual part of residual + JVP
+        }
+      } else if (OP == OP_ENERGY) {
+        T W, cf;
+        density<T>(gu, eps2, r, kind, inv_p, &W, &cf);
+        part += (double)(wq * det * W);
+      } else if (OP == OP_GRAD) {
+        T W, cf;
+        density<T>(gu, eps2, r, kind, inv_p, &W, &cf);
+        // no rho: dR/drho_e; wq carries rho, so divide it back out via wxy
+        const T wnr = tb.w[qx] * tb.w[qy] * tb.w[qz];
+        part -= (double)(wnr * det * cf * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
+      }
+      if (!REDUCE) {
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            T fh;
+            if (CURVED)
+              fh = wq * (adj[a][0] * Fo[o][0] + adj[a][1] * Fo[o][1] + adj[a][2] * Fo[o][2]);
+            else
+              fh = wq * sdet[a] * Fo[o][a];
+            g[o][a][qz] = fh;  // reuse the gradient registers for the fluxes
+          }
+        }
+      }
+    }
+    if (REDUCE) {
+      red[l] = (T)part;
+    } else {
+      // z-back: H0[c] = sum_qz B Fx, H1 = sum B Fy, H2 = sum D Fz -> in place over Y
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        T* h = Ys + (el * 2 + o) * L::Y + qxy;
+#pragma unroll
+        for (int c = 0; c < D1; ++c) {
+          T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+          for (int qz = 0; qz < NQ; ++qz) {
+            s0 += tb.B[qz * D1 + c] * g[o][0][qz];
+            s1 += tb.B[qz * D1 + c] * g[o][1][qz];
+            s2 += tb.D[qz * D1 + c] * g[o][2][qz];
+          }
+          h[c * NQ * NQ] = s0;
+          h[NQ * NQ * D1 + c * NQ * NQ] = s1;
+          h[2 * NQ * NQ * D1 + c * NQ * NQ] = s2;
+        }
+      }
     }
   }
   __syncthreads();
 
-  if (OP == OP_ENERGY || OP == OP_GRAD) {
-    // per-element deterministic reduction over its quadrature points
+  if (REDUCE) {
     const int lane = tid & 63, wv = tid >> 6;
     double* outd = static_cast<double*>(P.out0);
-    for (int el = wv; el < n_valid; el += kThreads / 64) {
-      const double s = wave_sum<T>(G1 + el * 3 * S::NQ3, S::NQ3, lane);
+    for (int el = wv; el < n_valid; el += NT / 64) {
+      const double s = wave_sum<T>(red + el * NQ * NQ, NQ * NQ, lane);
       if (lane == 0) outd[e0 + el] = s;
     }
     return;
   }
-  T* out0 = static_cast<T*>(P.out0) + (int64_t)e0 * S::Ne;
-  grad_backward<D1, NQ, EB, T>(sB, sD, G1, X, Y, out0, n_valid);
-  if (OP == OP_RESJVP) {
-    __syncthreads();
-    T* out1 = static_cast<T*>(P.out1) + (int64_t)e0 * S::Ne;
-    grad_backward<D1, NQ, EB, T>(sB, sD, G2, X, Y, out1, n_valid);
+
+  // ---- D: y-back: K0[b] = sum_qy B H0 ; K1[b] = sum_qy D H1 + B H2 -> X -------
+  for (int l = tid; l < EB * D1 * NQ; l += NT) {
+    const int el = l / (D1 * NQ), rem = l - el * (D1 * NQ);
+    const int c = rem / NQ, qx = rem - c * NQ;
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+      const T* h = Ys + (el * 2 + o) * L::Y + c * NQ * NQ + qx;
+      T h0[NQ], h1[NQ], h2[NQ];
+#pragma unroll
+      for (int qy = 0; qy < NQ; ++qy) {
+        h0[qy] = h[qy * NQ];
+        h1[qy] = h[NQ * NQ * D1 + qy * NQ];
+        h2[qy] = h[2 * NQ * NQ * D1 + qy * NQ];
+      }
+      T* k = Xs + (el * F + o) * L::X + c * D1 * NQ + qx;
+#pragma unroll
+      for (int b = 0; b < D1; ++b) {
+        T s0 = 0, s1 = 0;
+#pragma unroll
+        for (int qy = 0; qy < NQ; ++qy) {
+          s0 += tb.B[qy * D1 + b] * h0[qy];
+          s1 += tb.D[qy * D1 + b] * h1[qy] + tb.B[qy * D1 + b] * h2[qy];
+        }
+        k[b * NQ] = s0;
+        k[NQ * D1 * D1 + b * NQ] = s1;
+      }
+    }
   }
+  __syncthreads();
+
+  // ---- E: x-back: out[a] = sum_qx D K0 + B K1 -> E-vector --------------------
+  for (int l = tid; l < n_valid * D1 * D1; l += NT) {
+    const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
+#pragma unroll
+    for (int o = 0; o < O; ++o) {
+      const T* k = Xs + (el * F + o) * L::X + cb * NQ;
+      T k0[NQ], k1[NQ];
+#pragma unroll
+      for (int qx = 0; qx < NQ; ++qx) {
+        k0[qx] = k[qx];
+        k1[qx] = k[NQ * D1 * D1 + qx];
+      }
+      // output 0 is the JVP (or residual), output 1 the residual of residual + JVP
+      T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) +
+               (int64_t)(e0 + el) * Ne + cb * D1;
+#pragma unroll
+      for (int a = 0; a < D1; ++a) {
+        T s = 0;
+#pragma unroll
+        for (int qx = 0; qx < NQ; ++qx) s += tb.D[qx * D1 + a] * k0[qx] + tb.B[qx * D1 + a] * k1[qx];
+        out[a] = s;
+      }
+    }
+  }
+}
+
+template <int D1, int NQ, class T>
+Tab<D1, NQ, T> make_tab(const double* h) {
+  Tab<D1, NQ, T> t;
+  for (int i = 0; i < NQ * D1; ++i) {
+    t.B[i] = (T)h[i];
+    t.D[i] = (T)h[NQ * D1 + i];
+  }
+  for (int i = 0; i < NQ; ++i) {
+    t.w[i] = (T)h[2 * NQ * D1 + i];
+    t.xi[i] = (T)h[2 * NQ * D1 + NQ + i];
+  }
+  return t;
 }
 
 // Instantiate every operation, precision and geometry for one (D1, NQ) and
 // register the launchers in the dispatch table.
-#define FEOD_INSTANTIATE(DD, QQ)                                                              \
-  template <class T, int OP, bool CURVED>                                                     \
-  static hipError_t launch_##DD##_##QQ(const ElemParams& P, hipStream_t s) {                  \
-    constexpr int EB = Batch<DD, QQ, T>::EB;                                                  \
-    const int blocks = (P.E + EB - 1) / EB;                                                   \
-    if (blocks == 0) return hipSuccess;                                                       \
-    hipLaunchKernelGGL((element_kernel<DD, QQ, T, OP, CURVED>), dim3(blocks), dim3(kThreads), \
-                       0, s, P);                                                              \
-    return hipGetLastError();                                                                 \
-  }                                                                                           \
-  template <class T, bool CURVED>                                                             \
-  static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                   \
-    t.op[OP_RESIDUAL][CURVED] = &launch_##DD##_##QQ<T, OP_RESIDUAL, CURVED>;                  \
-    t.op[OP_JVP][CURVED] = &launch_##DD##_##QQ<T, OP_JVP, CURVED>;                            \
-    t.op[OP_RESJVP][CURVED] = &launch_##DD##_##QQ<T, OP_RESJVP, CURVED>;                      \
-    t.op[OP_ENERGY][CURVED] = &launch_##DD##_##QQ<T, OP_ENERGY, CURVED>;                      \
-    t.op[OP_GRAD][CURVED] = &launch_##DD##_##QQ<T, OP_GRAD, CURVED>;                          \
-  }                                                                                           \
-  ElemLaunchers make_launchers_##DD##_##QQ() {                                                \
-    ElemLaunchers L{};                                                                        \
-    L.D1 = DD;                                                                                \
-    L.NQ = QQ;                                                                                \
-    fill_##DD##_##QQ<double, false>(L.prec[0]);                                               \
-    fill_##DD##_##QQ<double, true>(L.prec[0]);                                                \
-    fill_##DD##_##QQ<float, false>(L.prec[1]);                                                \
-    fill_##DD##_##QQ<float, true>(L.prec[1]);                                                 \
-    L.eb[0] = Batch<DD, QQ, double>::EB;                                                      \
-    L.eb[1] = Batch<DD, QQ, float>::EB;                                                       \
-    return L;                                                                                 \
+#define FEOD_INSTANTIATE(DD, QQ)                                                                \
+  template <class T, int OP, bool CURVED>                                                       \
+  static hipError_t launch_##DD##_##QQ(const ElemParams& P, hipStream_t s) {                    \
+    constexpr int EB = Config<DD, QQ, T>::EB;                                                   \
+    constexpr int NT = Config<DD, QQ, T>::NT;                                                   \
+    const int blocks = (P.E + EB - 1) / EB;                                                     \
+    if (blocks == 0) return hipSuccess;                                                         \
+    const Tab<DD, QQ, T> tb = make_tab<DD, QQ, T>(P.htab);                                      \
+    hipLaunchKernelGGL((element_kernel<DD, QQ, T, OP, CURVED>), dim3(blocks), dim3(NT), 0, s, P, \
+                       tb);                                                                     \
+    return hipGetLastError();                                                                   \
+  }                                                                                             \
+  template <class T, bool CURVED>                                                               \
+  static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                     \
+    t.op[OP_RESIDUAL][CURVED] = &launch_##DD##_##QQ<T, OP_RESIDUAL, CURVED>;                    \
+    t.op[OP_JVP][CURVED] = &launch_##DD##_##QQ<T, OP_JVP, CURVED>;                              \
+    t.op[OP_RESJVP][CURVED] = &launch_##DD##_##QQ<T, OP_RESJVP, CURVED>;                        \
+    t.op[OP_ENERGY][CURVED] = &launch_##DD##_##QQ<T, OP_ENERGY, CURVED>;                        \
+    t.op[OP_GRAD][CURVED] = &launch_##DD##_##QQ<T, OP_GRAD, CURVED>;                            \
+  }                                                                                             \
+  ElemLaunchers make_launchers_##DD##_##QQ() {                                                  \
+    ElemLaunchers L{};                                                                          \
+    L.D1 = DD;                                                                                  \
+    L.NQ = QQ;                                                                                  \
+    fill_##DD##_##QQ<double, false>(L.prec[0]);                                                 \
+    fill_##DD##_##QQ<double, true>(L.prec[0]);                                                  \
+    fill_##DD##_##QQ<float, false>(L.prec[1]);                                                  \
+    fill_##DD##_##QQ<float, true>(L.prec[1]);                                                   \
+    L.eb[0] = Config<DD, QQ, double>::EB;                                                       \
+    L.eb[1] = Config<DD, QQ, float>::EB;                                                        \
+    return L;                                                                                   \
   }
 
 }  // namespace feod

@@ -42,6 +42,7 @@ struct feod_ctx {
   Tables1D tab;
   Lattice lat;
   std::vector<double> load, rho, verts;
+  std::vector<double> htab;  // B, D, w, xi concatenated (kernel argument source)
   bool has_rho = false;
   // workspace
   char* ws = nullptr;
@@ -213,9 +214,12 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
   P.nx = c->nx;
   P.ny = c->ny;
   P.nz = c->nz;
-  P.h[0] = 1.0 / c->nx;
-  P.h[1] = 1.0 / c->ny;
-  P.h[2] = 1.0 / c->nz;
+  P.htab = c->htab.data();
+  P.hinv[0] = c->nx;
+  P.hinv[1] = c->ny;
+  P.hinv[2] = c->nz;
+  P.det = 1.0 / ((double)c->nx * c->ny * c->nz);
+  for (int a = 0; a < 3; ++a) P.sdet[a] = P.det * P.hinv[a];
   const double p = p_override > 0 ? p_override : c->p;
   P.p = p;
   P.eps2 = c->eps * c->eps;
@@ -441,6 +445,8 @@ feod_status feod_setup_mesh(const feod_mesh_desc* d, feod_ctx** out) {
     return fail(nullptr, FEOD_EUNSUPPORTED, msg);
   }
   c->tab = make_tables(c->k, c->nq);
+  for (const auto* v : {&c->tab.B, &c->tab.D, &c->tab.qwts, &c->tab.qpts})
+    c->htab.insert(c->htab.end(), v->begin(), v->end());
   const int64_t nv = (int64_t)(c->nx + 1) * (c->ny + 1) * (c->nz + 1);
   if (d->vertices) {
     c->curved = true;

@@ -20,8 +20,11 @@ struct ElemParams {
   const void* tab;        // 1D tables in the kernel precision: B, D (nq x D1), w, xi (nq)
   void* out0;             // E-vector (kernel precision) or E doubles (energy, gradient)
   void* out1;             // second E-vector (residual + JVP)
+  const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
-  double h[3];            // affine element sizes
+  double hinv[3];         // affine meshes: 1/h per direction
+  double det;             // affine meshes: element volume h_x h_y h_z
+  double sdet[3];         // affine meshes: det * hinv
   double p, eps2, r, inv_p;
   int32_t powkind;
 };
