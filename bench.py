@@ -2,16 +2,18 @@
 
 One step = one Jacobian-vector apply J(u) v (G -> B -> dual-number D -> B^T ->
 G^T) in FP64 on the workload's seeded random u, v, with the inputs already
-resident in HBM.  value = n_dofs * steps / elapsed / 1e9 (GDOF/s).
+resident in HBM.  value = n_dofs * steps / elapsed / 1e9 (GDOF/s) on the
+32^3 Q3 p = 4 workload (c2).
 
-Also measured on the same line (not part of ``value``): the mixed-precision
-Jacobian apply, the residual, the fused residual + Jacobian apply, the
-adjoint-gradient time on the design workload, and the Newton-CG solve time,
-each with its own timing; the roofline of the dominant kernel from hipEvents
-recorded around every launch by the library; and the CPU oracle timed on a
-bounded sample.
+Also reported on the same JSON line (each timed separately, none of it part
+of ``value``): the mixed-precision Jacobian apply, the residual, the fused
+residual + Jacobian apply, the same applies on the other workloads, the
+Newton-CG and adjoint-gradient times on the design workload, the roofline of
+the dominant kernel from hipEvents the library records around every launch
+on its stream, and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
+       [--no-extras] [--no-cpu-baseline] [--calibrate-copy]
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ sys.path.insert(0, ROOT)
 METRIC = "GDOF/s of AD Jacobian-vector apply (FP64 vs mixed) + adjoint-gradient time"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6           # 256 CU * 2.4 GHz * 128 FLOP/clk (vector FP64 FMA)
-FP32_PEAK_TFS = 78.6           # scalar (non-packed) FP32 FMA: same lane rate as FP64
+FP32_PEAK_TFS = 78.6           # non-packed FP32 FMA: same lane rate as FP64
 
 
 def log(*a):
@@ -50,6 +52,7 @@ def timed_loop(fn, steps, warmup):
 
 
 def kernel_profile(prob, fn, steps):
+    """Per-kernel average durations from the library's own hipEvents."""
     import torch
     torch.cuda.synchronize()
     prob.profile(True)
@@ -76,6 +79,65 @@ def roofline(prob, op, prec, stats, kernel):
               "algorithmic_flops": flops, "achieved_GBs": gbs, "achieved_TFLOPs": tfs,
               "traffic": None})
     return r
+
+
+def apply_rows(prob, u, v, w, args, only=None):
+    """GDOF/s and kernel roofline of the applies of one workload."""
+    import torch
+    jv = torch.empty_like(u)
+    r = torch.empty_like(u)
+    N = w.n_dofs
+    cases = [("jvp_fp64", lambda: prob.jacobian_apply(u, v, out=jv), "jvp", "fp64", "element_jvp_f64"),
+             ("jvp_mixed", lambda: prob.jacobian_apply(u, v, out=jv, prec="mixed"), "jvp", "mixed",
+              "element_jvp_f32"),
+             ("residual_fp64", lambda: prob.residual(u, out=r), "residual", "fp64", "element_residual_f64"),
+             ("residual_jvp_fp64", lambda: prob.jacobian_apply(u, v, out=jv, residual_out=r),
+              "resjvp", "fp64", "element_resjvp_f64")]
+    out = {}
+    for name, fn, op, prec, kern in cases:
+        if only is not None and name not in only:
+            continue
+        t = timed_loop(fn, args.steps, args.warmup)
+        st = kernel_profile(prob, fn, min(args.steps, 50))
+        rl = roofline(prob, op, prec, st, kern)
+        gt = st.get("gather_transpose", st.get("gather_transpose2", {"avg_ms": 0.0}))
+        out[name] = {"GDOF/s": N / (t * 1e-3) / 1e9, "us_per_apply": t * 1e3, "kernel_us": rl["avg_us"],
+                     "kernel_bound": rl["bound"], "kernel_frac": rl["frac"],
+                     "kernel_TFLOPs": rl["achieved_TFLOPs"], "kernel_GBs": rl["achieved_GBs"],
+                     "gather_t_us": gt["avg_ms"] * 1e3, "roofline": rl}
+    if "jvp_fp64" in out and "jvp_mixed" in out:
+        out["jvp_mixed"]["speedup_vs_fp64_apply"] = out["jvp_mixed"]["GDOF/s"] / out["jvp_fp64"]["GDOF/s"]
+    return out
+
+
+def solve_rows(feod, WORKLOADS, make_inputs, dev):
+    """Newton-CG and adjoint-gradient wall times on the design workload (c4)."""
+    import torch
+    out = {}
+    w = WORKLOADS["c4"]
+    ii = make_inputs(w)
+    pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, rho=ii["rho"], device=dev)
+    b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load, device=dev)
+    u, rep = pb.newton_solve(rtol=1e-10)
+    out["c4_newton_fp64"] = {k: rep[k] for k in ("newton_iters", "cg_iters_total", "res_final", "ref_norm",
+                                                 "seconds")}
+    g64 = None
+    for prec in ("fp64", "mixed"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g, lam, rep = pb.adjoint_gradient(u, b, rtol=1e-10, prec=prec)
+        torch.cuda.synchronize()
+        row = {"ms": (time.perf_counter() - t0) * 1e3, "cg_iters": rep["cg_iters_total"],
+               "refine_iters": rep["refine_iters"], "res_final_rel": rep["res_final"] / rep["ref_norm"]}
+        if g64 is None:
+            g64 = g.clone()
+        else:
+            row["grad_rel_err_vs_fp64"] = float(torch.linalg.norm(g - g64) / torch.linalg.norm(g64))
+        out[f"c4_adjoint_gradient_{prec}"] = row
+    log(f"[bench] solves: {out}")
+    del pb
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(w, inp, budget_s=12.0):
@@ -105,6 +167,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -124,8 +188,14 @@ def main():
     u = torch.as_tensor(inp["u"], device=dev)
     v = torch.as_tensor(inp["v"], device=dev)
     jv = torch.empty_like(u)
-    r = torch.empty_like(u)
     N = w.n_dofs
+
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def jvp64():
         prob.jacobian_apply(u, v, out=jv)
@@ -137,26 +207,27 @@ def main():
     roof = roofline(prob, "jvp", "fp64", stats, "element_jvp_f64")
     log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s; kernels {stats}")
 
-    rows = {"jvp_fp64": {"GDOF/s": value, "us_per_apply": ms * 1e3}}
+    rows = {w.name: {"jvp_fp64": {"GDOF/s": value, "us_per_apply": ms * 1e3, "kernel_us": roof["avg_us"],
+                                  "kernel_bound": roof["bound"], "kernel_frac": roof["frac"]}}}
     if not args.no_extras:
-        def jvp32():
-            prob.jacobian_apply(u, v, out=jv, prec="mixed")
-
-        def res64():
-            prob.residual(u, out=r)
-
-        def resjvp64():
-            prob.jacobian_apply(u, v, out=jv, residual_out=r)
-        for name, fn, op, prec, kern in [("jvp_mixed", jvp32, "jvp", "mixed", "element_jvp_f32"),
-                                         ("residual_fp64", res64, "residual", "fp64", "element_residual_f64"),
-                                         ("residual_jvp_fp64", resjvp64, "resjvp", "fp64", "element_resjvp_f64")]:
-            t = timed_loop(fn, args.steps, args.warmup)
-            st = kernel_profile(prob, fn, min(args.steps, 50))
-            rl = roofline(prob, op, prec, st, kern)
-            rows[name] = {"GDOF/s": N / (t * 1e-3) / 1e9, "us_per_apply": t * 1e3,
-                          "kernel_us": rl["avg_us"], "kernel_frac": rl["frac"], "kernel_bound": rl["bound"]}
-            log(f"[bench] {name}: {rows[name]}")
-        rows["jvp_mixed"]["speedup_vs_fp64_apply"] = rows["jvp_mixed"]["GDOF/s"] / value
+        rows[w.name].update(apply_rows(prob, u, v, w, args,
+                                       only=("jvp_mixed", "residual_fp64", "residual_jvp_fp64")))
+        rows[w.name]["jvp_mixed"]["speedup_vs_fp64_apply"] = rows[w.name]["jvp_mixed"]["GDOF/s"] / value
+        log(f"[bench] {w.name} rows: {rows[w.name]}")
+        del prob, u, v, jv
+        torch.cuda.empty_cache()
+        for name in [x for x in ("c2", "c3", "c4", "c5") if x != w.name]:
+            wl = WORKLOADS[name]
+            ii = make_inputs(wl)
+            pb = feod.Problem(wl.nx, wl.ny, wl.nz, wl.k, wl.nq, wl.p, wl.eps, vertices=ii["vertices"],
+                              rho=ii["rho"], device=dev)
+            uu = torch.as_tensor(ii["u"], device=dev)
+            vv = torch.as_tensor(ii["v"], device=dev)
+            rows[name] = apply_rows(pb, uu, vv, wl, args, only=("jvp_fp64", "jvp_mixed", "residual_fp64"))
+            log(f"[bench] {name}: { {k: (x['GDOF/s'], x['kernel_us'], x['kernel_frac']) for k, x in rows[name].items()} }")
+            del pb, uu, vv
+            torch.cuda.empty_cache()
+        rows["solves"] = solve_rows(feod, WORKLOADS, make_inputs, dev)
 
     cpu = None
     if not args.no_cpu_baseline:

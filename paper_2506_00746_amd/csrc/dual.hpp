@@ -26,20 +26,7 @@ template <class T> __device__ __forceinline__ dual<T> operator*(dual<T> a, T s) 
 template <class T> __device__ __forceinline__ dual<T> operator*(T s, dual<T> a) { return {a.v * s, a.d * s}; }
 
 // Real-valued overloads so the pointwise code can be written once for T and dual<T>.
-__device__ __forceinline__ double fe_sqrt(double x) { return sqrt(x); }
-__device__ __forceinline__ float fe_sqrt(float x) { return sqrtf(x); }
 __device__ __forceinline__ double fe_pow(double x, double r) { return pow(x, r); }
 __device__ __forceinline__ float fe_pow(float x, float r) { return powf(x, r); }
-
-template <class T> __device__ __forceinline__ dual<T> fe_sqrt(dual<T> x) {
-  T s = fe_sqrt(x.v);
-  return {s, x.d / (T(2) * s)};
-}
-template <class T> __device__ __forceinline__ dual<T> fe_pow(dual<T> x, T r) {
-  T pv = fe_pow(x.v, r);
-  return {pv, r * pv / x.v * x.d};
-}
-
-template <class T> __device__ __forceinline__ T make_const(T c) { return c; }
 
 }  // namespace feod

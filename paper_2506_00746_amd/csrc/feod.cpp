@@ -238,7 +238,7 @@ const char* op_name(int op, int prec) {
 }
 
 feod_status run_element(feod_ctx* c, int op, int prec, const ElemParams& P) {
-  ElemLaunch fn = c->L->prec[prec].op[op][c->curved ? 1 : 0];
+  ElemLaunch fn = c->L->prec[prec].op[op][c->curved ? 1 : 0][P.powkind];
   if (!fn) return fail(c, FEOD_EUNSUPPORTED, "operation not built for this (k, nq)");
   return timed(c, op_name(op, prec), [&] { return fn(P, c->stream); });
 }

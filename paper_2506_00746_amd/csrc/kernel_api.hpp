@@ -29,12 +29,22 @@ struct ElemParams {
   int32_t powkind;
 };
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2).  Renumber them so that XCD j processes one contiguous range of the
+// logical batches: neighbouring elements (and DOFs) then share an L2.
+constexpr int kNumXcd = 8;
+__device__ __forceinline__ int xcd_remap(int w, int n) {
+  const int q = n / kNumXcd, r = n % kNumXcd;
+  const int j = w % kNumXcd, i = w / kNumXcd;
+  return j * q + (j < r ? j : r) + i;
+}
+
 using ElemLaunch = hipError_t (*)(const ElemParams&, hipStream_t);
 
 struct ElemLaunchers {
   int D1, NQ;
   struct PerPrec {
-    ElemLaunch op[OP_COUNT][2];  // [op][curved]
+    ElemLaunch op[OP_COUNT][2][5];  // [op][curved][PowKind]
   } prec[2];                     // [0] FP64, [1] FP32
   int eb[2];
 };

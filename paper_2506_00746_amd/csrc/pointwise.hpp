@@ -12,39 +12,70 @@ namespace feod {
 // a^r for the exponents the p-Laplacian workloads use, by sqrt chains where
 // possible; POW_GENERIC falls back to pow() (PowKind is in kernel_api.hpp).
 
-__device__ __forceinline__ double one_like(double) { return 1.0; }
-__device__ __forceinline__ float one_like(float) { return 1.0f; }
-template <class T> __device__ __forceinline__ dual<T> one_like(dual<T>) { return {T(1), T(0)}; }
+// 1/sqrt(x): the hardware reciprocal square root refined by Newton steps on
+// f(y) = 1/y^2 - x (y <- y (3 - x y^2) / 2), two for FP64, none for FP32
+// (already within an ulp there).
+__device__ __forceinline__ double fe_rsqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * (1.5 - hx * y * y);
+  y = y * (1.5 - hx * y * y);
+  return y;
+}
+__device__ __forceinline__ float fe_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
-template <class S, class T>
-__device__ __forceinline__ S apow(S a, T r, int kind) {
-  switch (kind) {
-    case POW_ZERO: return one_like(a);
-    case POW_QUARTER: return fe_sqrt(fe_sqrt(a));
-    case POW_HALF: return fe_sqrt(a);
-    case POW_ONE: return a;
-    default: return fe_pow(a, r);
+// a^r and, for dual numbers, d(a^r) = r a^(r-1) da, without divisions:
+//   r = 1/2:  a^r = a t, t = a^(-1/2);  d = t da / 2
+//   r = 1/4:  a^r = s u, s = a t, u = s^(-1/2);  d = a^r t^2 da / 4
+template <int PK, class T>
+__device__ __forceinline__ T apow(T a, T r) {
+  if constexpr (PK == POW_ZERO) return T(1);
+  else if constexpr (PK == POW_QUARTER) {
+    const T s = a * fe_rsqrt(a);
+    return s * fe_rsqrt(s);
+  } else if constexpr (PK == POW_HALF) return a * fe_rsqrt(a);
+  else if constexpr (PK == POW_ONE) return a;
+  else return fe_pow(a, r);
+}
+
+template <int PK, class T>
+__device__ __forceinline__ dual<T> apow(dual<T> a, T r) {
+  if constexpr (PK == POW_ZERO) {
+    return {T(1), T(0)};
+  } else if constexpr (PK == POW_QUARTER) {
+    const T t = fe_rsqrt(a.v);
+    const T s = a.v * t;
+    const T c = s * fe_rsqrt(s);
+    return {c, T(0.25) * c * t * t * a.d};
+  } else if constexpr (PK == POW_HALF) {
+    const T t = fe_rsqrt(a.v);
+    return {a.v * t, T(0.5) * t * a.d};
+  } else if constexpr (PK == POW_ONE) {
+    return a;
+  } else {
+    const T pv = fe_pow(a.v, r);
+    return {pv, r * pv / a.v * a.d};
   }
 }
 
 template <class T> __device__ __forceinline__ T value_of(T x) { return x; }
 template <class T> __device__ __forceinline__ T value_of(dual<T> x) { return x.v; }
 
-// F = a^r g with a = eps2 + |g|^2; also returns a^r (value) through coef.
-template <class S, class T>
-__device__ __forceinline__ void flux(const S g[3], T eps2, T r, int kind, S F[3]) {
+// F = a^r g with a = eps2 + |g|^2.
+template <int PK, class S, class T>
+__device__ __forceinline__ void flux(const S g[3], T eps2, T r, S F[3]) {
   S a = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + eps2;
-  S c = apow(a, r, kind);
+  S c = apow<PK>(a, r);
   F[0] = c * g[0];
   F[1] = c * g[1];
   F[2] = c * g[2];
 }
 
 // Energy density W(g) = (1/p) a^(p/2) = a * a^r / p and the scalar a^r.
-template <class T>
-__device__ __forceinline__ void density(const T g[3], T eps2, T r, int kind, T inv_p, T* W, T* coef) {
+template <int PK, class T>
+__device__ __forceinline__ void density(const T g[3], T eps2, T r, T inv_p, T* W, T* coef) {
   T a = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + eps2;
-  T c = apow(a, r, kind);
+  T c = apow<PK>(a, r);
   *W = a * c * inv_p;
   *coef = c;
 }

@@ -25,7 +25,7 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_kernel(const int32_t* __
                                                                const double* __restrict__ bm,
                                                                double* __restrict__ out0,
                                                                double* __restrict__ out1, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
+  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kVecThreads + threadIdx.x;
   if (i >= n) return;
   const int j0 = off[i], j1 = off[i + 1];
   double s0 = 0, s1 = 0;
