@@ -139,6 +139,15 @@ feod_status feod_bind_workspace(feod_ctx* ctx, void* dev_ptr, size_t bytes);
 
 feod_status feod_sizes(const feod_ctx* ctx, int64_t* n_dofs, int64_t* n_elems);
 
+/* How G and G^T find element DOFs (paper: G is "topological", independent
+ * of the solution).  FEOD_MAPS_LATTICE (default): the element-to-DOF map and
+ * its transpose are computed from the structured node lattice inside the
+ * kernels; FEOD_MAPS_EXPLICIT: they are read from the stored map (E x (k+1)^3
+ * int32) and transposed map (CSR).  Both give bitwise identical results: G^T
+ * sums each DOF's element contributions in ascending E-vector order. */
+enum { FEOD_MAPS_LATTICE = 0, FEOD_MAPS_EXPLICIT = 1 };
+feod_status feod_set_map_mode(feod_ctx* ctx, int32_t mode);
+
 /* Change the stream later calls enqueue on. */
 feod_status feod_set_stream(feod_ctx* ctx, void* stream);
 
@@ -207,8 +216,8 @@ feod_status feod_kernel_cost(const feod_ctx* ctx, int32_t op, feod_prec prec,
 /* Host copies of setup data, for inspection without a GPU.
  * Tables: nodes[k+1], qpts[nq], qwts[nq], Bhat[nq*(k+1)], Dhat[nq*(k+1)]
  * (row q, column a).  Maps: emap[E*(k+1)^3] (global DOF or -1 on Dirichlet
- * DOFs), toff[N+1] and tidx[toff[N]] (E-vector positions summed into each
- * DOF, ascending).  load: b (N, unmasked). Any pointer may be NULL. */
+ * DOFs), toff[N+1] and tidx[toff[N]] (E-vector positions e*(k+1)^3 + local
+ * node of the entries summed into each DOF, by ascending element).  load: b (N, unmasked). Any pointer may be NULL. */
 feod_status feod_host_tables(const feod_ctx* ctx, double* nodes, double* qpts,
                              double* qwts, double* Bhat, double* Dhat);
 feod_status feod_host_maps(const feod_ctx* ctx, int32_t* emap, int32_t* toff,

@@ -17,8 +17,9 @@
 //                     Quadrature-point data never leaves registers.
 //   D  y-back         line (c,qx) -> LDS.
 //   E  x-back         line (c,b): D1 element residual entries written
-//                     contiguously to the output E-vector (G^T is the separate
-//                     deterministic gather).
+//                     contiguously to the output E-vector, laid out
+//                     [ez][ey][c][b][ex][a] (G^T is the separate deterministic
+//                     gather).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -47,16 +48,33 @@ struct Config {
   static constexpr int NT = NQ * NQ <= 25 ? 128 : 256;
   static constexpr int EB0 = NT / (NQ * NQ);
   static constexpr int EB = EB0 < 1 ? 1 : EB0;
+  // SEQ: the two input fields of a Jacobian action pass through the x-pass
+  // buffer one after the other (halves it); needs one phase-C line per thread.
+  static constexpr bool SEQ = false;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
   static constexpr int NT = 256;
   static constexpr int EB = 3;
+  static constexpr bool SEQ = true;
 };
 
+// Loops over a table index are fully unrolled for small D1/NQ (table entries
+// become scalar operands); for large ones they run at runtime so that only one
+// slice of the table is live in scalar registers.
+template <int N>
+struct Unroll {
+  static constexpr bool full = N <= 6;
+};
+
+// LDS layout.  The x-pass buffer is [c][qx][b]; when D1 is a multiple of 8
+// its qx stride is padded by one scalar, otherwise the NQ distinct qx columns
+// phase C reads at once would fall on only two LDS banks.
 template <int D1, int NQ, int F, int O>
 struct Lds {
-  static constexpr int XS = NQ * D1 * D1;         // one x-pass output block [c][qx][b]
-  static constexpr int X = F * 2 * XS;            // x-pass output of F fields (reused for K)
+  static constexpr int XQ = D1 % 8 ? D1 : D1 + 1;  // qx stride
+  static constexpr int XC = NQ * XQ;              // c stride
+  static constexpr int XS = D1 * XC;              // one x-pass output block [c][qx][b]
+  static constexpr int X = (F > O ? F : O) * 2 * XS;  // x-pass output of F fields (reused for K)
   static constexpr int H = O * 3 * D1 * NQ * NQ;  // z-back output [o][d][c][qy][qx]
   static constexpr int per_elem = X + H + 24;
 };
@@ -71,18 +89,111 @@ __device__ __forceinline__ double wave_sum(const T* vals, int n, int lane) {
   return s;
 }
 
+// Phase A for NF fields: gather lines (c,b) of the fields through the map and
+// contract in x.  Slot f of the x-pass buffer receives field src[f].
+template <int D1, int NQ, int EB, int NT, int XSTRIDE, int XQ, int NF, class T, class TB>
+__device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const double* const (&src)[NF],
+                                        T* Xs, int e0, int n_valid, int tid, const int (*sE)[3]) {
+  constexpr int Ne = D1 * D1 * D1;
+  constexpr int XS = D1 * NQ * XQ;
+  for (int l = tid; l < EB * D1 * D1; l += NT) {
+#if FEOD_EVEC_ROWMAJOR
+    const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: consecutive elements of the row
+#else
+    const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
+#endif
+    const int c = cb / D1, b = cb - c * D1;
+    T in[NF][D1];
+    if (el < n_valid && P.emap != nullptr) {
+      const int32_t* m = P.emap + (int64_t)(e0 + el) * Ne + cb * D1;
+#pragma unroll
+      for (int a = 0; a < D1; ++a) {
+        const int idx = m[a];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in[f][a] = idx >= 0 ? (T)src[f][idx] : T(0);
+      }
+    } else if (el < n_valid) {
+      // the same map computed from the lattice: node (k ex + a, k ey + b, k ez + c),
+      // Dirichlet nodes (on the cube's boundary) read as 0
+      const int I0 = P.k * sE[el][0], J = P.k * sE[el][1] + b, K = P.k * sE[el][2] + c;
+      const bool row = J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
+      const int64_t base = I0 + (int64_t)P.Lx * (J + (int64_t)P.Ly * K);
+#pragma unroll
+      for (int a = 0; a < D1; ++a) {
+        const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in[f][a] = ok ? (T)src[f][base + a] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+#pragma unroll
+        for (int a = 0; a < D1; ++a) in[f][a] = 0;
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T* x = Xs + el * XSTRIDE + f * 2 * XS + c * NQ * XQ + b;
+#pragma unroll(Unroll<NQ>::full ? NQ : 1)
+      for (int qx = 0; qx < NQ; ++qx) {
+        T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.D[qx * D1] * in[f][0];
+#pragma unroll
+        for (int a = 1; a < D1; ++a) {
+          s0 += tb.B[qx * D1 + a] * in[f][a];
+          s1 += tb.D[qx * D1 + a] * in[f][a];
+        }
+        x[qx * XQ] = s0;
+        x[XS + qx * XQ] = s1;
+      }
+    }
+  }
+}
+
+// Phase C forward for one field: y-pass of column (qx,qy) from x-pass slot
+// xs, then z-pass into gf[3][NQ] (reference gradient x, y, z at each qz).
+template <int D1, int NQ, int XQ, class T, class TB>
+__device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const T (&By)[D1],
+                                               const T (&Dy)[D1], int qx, T (&gf)[3][NQ]) {
+  constexpr int XS = D1 * NQ * XQ;
+#pragma unroll
+  for (int qz = 0; qz < NQ; ++qz) gf[0][qz] = gf[1][qz] = gf[2][qz] = T(0);
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
+  for (int c = 0; c < D1; ++c) {
+    const T* x0 = xs + (c * NQ + qx) * XQ;
+    const T* x1 = x0 + XS;
+    // y-pass for this column: Y0 = D_y X0 (d/dy), Y1 = B_y X0 (d/dz), Y2 = B_y X1 (d/dx)
+    T y0 = Dy[0] * x0[0], y1 = By[0] * x0[0], y2 = By[0] * x1[0];
+#pragma unroll
+    for (int b = 1; b < D1; ++b) {
+      y0 += Dy[b] * x0[b];
+      y1 += By[b] * x0[b];
+      y2 += By[b] * x1[b];
+    }
+    // z-pass: gx += B_z Y2, gy += B_z Y0, gz += D_z Y1
+#pragma unroll
+    for (int qz = 0; qz < NQ; ++qz) {
+      gf[0][qz] += tb.B[qz * D1 + c] * y2;
+      gf[1][qz] += tb.B[qz * D1 + c] * y0;
+      gf[2][qz] += tb.D[qz * D1 + c] * y1;
+    }
+  }
+}
+
 template <int D1, int NQ, class T, int OP, bool CURVED, int PK>
 __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
-  constexpr int NT = Config<D1, NQ, T>::NT;
-  constexpr int EB = Config<D1, NQ, T>::EB;
+  using C = Config<D1, NQ, T>;
+  constexpr int NT = C::NT;
+  constexpr int EB = C::EB;
   constexpr int Ne = D1 * D1 * D1;
   constexpr int NQ2 = NQ * NQ;
   constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD) ? 2 : 1;  // input fields
   constexpr int O = (OP == OP_RESJVP) ? 2 : 1;                                    // output fields
   constexpr bool REDUCE = (OP == OP_ENERGY || OP == OP_GRAD);
-  using L = Lds<D1, NQ, F, O>;
+  constexpr bool SEQ = C::SEQ && F == 2;
+  static_assert(!SEQ || EB * NQ2 <= NT, "sequential fields need one phase-C line per thread");
+  constexpr int FX = SEQ ? 1 : F;  // fields resident in the x-pass buffer at once
+  using L = Lds<D1, NQ, FX, O>;
   __shared__ T smem[EB * L::per_elem];
-  __shared__ T sB[NQ * D1], sD[NQ * D1];
+  __shared__ T sB[NQ * L::XQ], sD[NQ * L::XQ];  // table rows, same padded stride
   T* Xs = smem;                 // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
   T* Hs = Xs + EB * L::X;       // [el][o][d][c][qy][qx]; per-line sums for reductions
   T* Vs = Hs + EB * L::H;       // [el][24] vertex coordinates
@@ -90,10 +201,19 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EB;
   const int n_valid = min(EB, P.E - e0);
+  __shared__ int sE[EB][3];  // (ex, ey, ez) of each element of the batch
+  if (tid < EB) {
+    const int e = e0 + tid;
+    const int ex = e % P.nx, t = e / P.nx;
+    sE[tid][0] = ex;
+    sE[tid][1] = t % P.ny;
+    sE[tid][2] = t / P.ny;
+  }
 
   for (int i = tid; i < NQ * D1; i += NT) {
-    sB[i] = tb.B[i];
-    sD[i] = tb.D[i];
+    const int q = i / D1, a = i - q * D1;
+    sB[q * L::XQ + a] = tb.B[i];
+    sD[q * L::XQ + a] = tb.D[i];
   }
   if (CURVED) {
     for (int i = tid; i < EB * 24; i += NT) {
@@ -109,83 +229,54 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
     }
   }
 
-  // ---- A: gather + x-pass: X[f][0][c][qx][b] = sum_a B u, X[f][1] = sum_a D u --
-  for (int l = tid; l < EB * D1 * D1; l += NT) {
-    const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
-    const int c = cb / D1, b = cb - c * D1;
-    T in[F][D1];
-    if (el < n_valid) {
-      const int32_t* m = P.emap + (int64_t)(e0 + el) * Ne + cb * D1;
-#pragma unroll
-      for (int a = 0; a < D1; ++a) {
-        const int idx = m[a];
-        in[0][a] = idx >= 0 ? (T)P.u[idx] : T(0);
-        if constexpr (F == 2) in[1][a] = idx >= 0 ? (T)P.v[idx] : T(0);
-      }
-    } else {
-#pragma unroll
-      for (int f = 0; f < F; ++f)
-#pragma unroll
-        for (int a = 0; a < D1; ++a) in[f][a] = 0;
-    }
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      T* x = Xs + el * L::X + f * 2 * L::XS + c * NQ * D1 + b;
-#pragma unroll
-      for (int qx = 0; qx < NQ; ++qx) {
-        T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.D[qx * D1] * in[f][0];
-#pragma unroll
-        for (int a = 1; a < D1; ++a) {
-          s0 += tb.B[qx * D1 + a] * in[f][a];
-          s1 += tb.D[qx * D1 + a] * in[f][a];
-        }
-        x[qx * D1] = s0;
-        x[L::XS + qx * D1] = s1;
-      }
-    }
+  __syncthreads();  // sE, tables and vertices visible to every thread
+
+  // ---- A: gather + x-pass ---------------------------------------------------
+  if constexpr (F == 2 && !SEQ) {
+    const double* const src[2] = {P.u, P.v};
+    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+  } else {
+    const double* const src[1] = {P.u};
+    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
   }
   __syncthreads();
 
   // ---- C: y-pass + z-pass -> D -> z-back, one (qx,qy) column per line ---------
   const T eps2 = (T)P.eps2, r = (T)P.r, inv_p = (T)P.inv_p;
+  T g[F][3][NQ];
+  if constexpr (SEQ) {
+    // field u: columns into registers, then the x-pass buffer takes field v
+    const int l = tid;
+    if (l < EB * NQ2) {
+      const int el = l / NQ2, qxy = l - el * NQ2;
+      const int qy = qxy / NQ, qx = qxy - qy * NQ;
+      T By[D1], Dy[D1];
+#pragma unroll
+      for (int b = 0; b < D1; ++b) {
+        By[b] = sB[qy * L::XQ + b];
+        Dy[b] = sD[qy * L::XQ + b];
+      }
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[0]);
+    }
+    __syncthreads();
+    const double* const src[1] = {P.v};
+    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    __syncthreads();
+  }
   for (int l = tid; l < EB * NQ2; l += NT) {
     const int el = l / NQ2, qxy = l - el * NQ2;
     const int qy = qxy / NQ, qx = qxy - qy * NQ;
     T By[D1], Dy[D1];
 #pragma unroll
     for (int b = 0; b < D1; ++b) {
-      By[b] = sB[qy * D1 + b];
-      Dy[b] = sD[qy * D1 + b];
+      By[b] = sB[qy * L::XQ + b];
+      Dy[b] = sD[qy * L::XQ + b];
     }
-    T g[F][3][NQ];
+    if constexpr (SEQ) {
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[1]);
+    } else {
 #pragma unroll
-    for (int c = 0; c < D1; ++c) {
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        const T* x0 = Xs + el * L::X + f * 2 * L::XS + (c * NQ + qx) * D1;
-        const T* x1 = x0 + L::XS;
-        // y-pass for this column: Y0 = D_y X0 (d/dy), Y1 = B_y X0 (d/dz), Y2 = B_y X1 (d/dx)
-        T y0 = Dy[0] * x0[0], y1 = By[0] * x0[0], y2 = By[0] * x1[0];
-#pragma unroll
-        for (int b = 1; b < D1; ++b) {
-          y0 += Dy[b] * x0[b];
-          y1 += By[b] * x0[b];
-          y2 += By[b] * x1[b];
-        }
-        // z-pass: gx += B_z Y2, gy += B_z Y0, gz += D_z Y1
-#pragma unroll
-        for (int qz = 0; qz < NQ; ++qz) {
-          if (c == 0) {
-            g[f][0][qz] = tb.B[qz * D1] * y2;
-            g[f][1][qz] = tb.B[qz * D1] * y0;
-            g[f][2][qz] = tb.D[qz * D1] * y1;
-          } else {
-            g[f][0][qz] += tb.B[qz * D1 + c] * y2;
-            g[f][1][qz] += tb.B[qz * D1 + c] * y0;
-            g[f][2][qz] += tb.D[qz * D1 + c] * y1;
-          }
-        }
-      }
+      for (int f = 0; f < F; ++f) column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X + f * 2 * L::XS, By, Dy, qx, g[f]);
     }
     const bool valid = el < n_valid;
     const T rho = (P.rho != nullptr && valid) ? (T)P.rho[e0 + el] : T(1);
@@ -295,7 +386,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         T* h = Hs + el * L::H + o * 3 * D1 * NQ2 + qxy;
-#pragma unroll
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
         for (int c = 0; c < D1; ++c) {
           T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.D[c] * g[o][2][0];
 #pragma unroll
@@ -337,8 +428,8 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
         h1[qy] = h[D1 * NQ2 + qy * NQ];
         h2[qy] = h[2 * D1 * NQ2 + qy * NQ];
       }
-      T* k = Xs + el * L::X + o * 2 * L::XS + (c * NQ + qx) * D1;
-#pragma unroll
+      T* k = Xs + el * L::X + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
       for (int b = 0; b < D1; ++b) {
         T s0 = tb.B[b] * h0[0], s1 = tb.D[b] * h1[0];
         s1 += tb.B[b] * h2[0];
@@ -356,22 +447,31 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   __syncthreads();
 
   // ---- E: x-back: out[a] = sum_qx D K0 + B K1 -> E-vector --------------------
-  for (int l = tid; l < n_valid * D1 * D1; l += NT) {
+  for (int l = tid; l < EB * D1 * D1; l += NT) {
+#if FEOD_EVEC_ROWMAJOR
+    const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: adjacent E-vector stretches
+    const int c = cb / D1, b = cb - c * D1;
+    if (el >= n_valid) continue;
+    const int64_t pos = ((((int64_t)sE[el][2] * P.ny + sE[el][1]) * D1 + c) * D1 + b) * P.nx * D1 +
+                        (int64_t)sE[el][0] * D1;
+#else
     const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
     const int c = cb / D1, b = cb - c * D1;
+    if (el >= n_valid) continue;
+    const int64_t pos = (int64_t)(e0 + el) * Ne + cb * D1;
+#endif
 #pragma unroll
     for (int o = 0; o < O; ++o) {
-      const T* k = Xs + el * L::X + o * 2 * L::XS + c * NQ * D1 + b;
+      const T* k = Xs + el * L::X + o * 2 * L::XS + c * L::XC + b;
       T k0[NQ], k1[NQ];
 #pragma unroll
       for (int qx = 0; qx < NQ; ++qx) {
-        k0[qx] = k[qx * D1];
-        k1[qx] = k[L::XS + qx * D1];
+        k0[qx] = k[qx * L::XQ];
+        k1[qx] = k[L::XS + qx * L::XQ];
       }
       // output 0 is the JVP (or residual); output 1 the residual of residual + JVP
-      T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) +
-               (int64_t)(e0 + el) * Ne + cb * D1;
-#pragma unroll
+      T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) + pos;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
       for (int a = 0; a < D1; ++a) {
         T s = tb.D[a] * k0[0];
         s += tb.B[a] * k1[0];

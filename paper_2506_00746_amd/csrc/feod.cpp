@@ -44,6 +44,7 @@ struct feod_ctx {
   std::vector<double> load, rho, verts;
   std::vector<double> htab;  // B, D, w, xi concatenated (kernel argument source)
   bool has_rho = false;
+  bool explicit_maps = false;  // G / G^T from stored maps (true) or computed from the lattice
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -204,7 +205,11 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
   ElemParams P{};
   P.u = u;
   P.v = v;
-  P.emap = c->d_emap;
+  P.emap = c->explicit_maps ? c->d_emap : nullptr;
+  P.k = c->k;
+  P.Lx = (int32_t)c->lat.Lx;
+  P.Ly = (int32_t)c->lat.Ly;
+  P.Lz = (int32_t)c->lat.Lz;
   P.rho = c->has_rho ? c->d_rho : nullptr;
   P.verts = c->curved ? c->d_verts : nullptr;
   P.tab = prec ? (const void*)c->d_tab32 : (const void*)c->d_tab64;
@@ -243,29 +248,29 @@ feod_status run_element(feod_ctx* c, int op, int prec, const ElemParams& P) {
   return timed(c, op_name(op, prec), [&] { return fn(P, c->stream); });
 }
 
+// G^T of one or two E-vectors: y0 = G^T Y0 - bm (bm may be null), y1 = G^T Y1
+hipError_t gather_t(feod_ctx* c, const void* Y0, const void* Y1, bool fp32, const double* bm, double* y0,
+                    double* y1) {
+  if (c->explicit_maps)
+    return launch_gather_t(c->d_toff, c->d_tidx, Y0, Y1, fp32, bm, y0, y1, c->lat.N, c->stream);
+  LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz};
+  return launch_gather_t_lattice(d, Y0, Y1, fp32, bm, y0, y1, c->lat.N, c->stream);
+}
+
 // r = M(A(Mu) - b) (bm != null) or M A(Mu)
 feod_status apply_residual(feod_ctx* c, const double* u, double* r, int prec) {
   TRY(run_element(c, OP_RESIDUAL, prec, params(c, u, nullptr, c->d_Y0, nullptr, prec)));
-  return timed(c, "gather_transpose", [&] {
-    return launch_gather_t(c->d_toff, c->d_tidx, c->d_Y0, nullptr, prec == 1, c->d_bm, r, nullptr,
-                           c->lat.N, c->stream);
-  });
+  return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, c->d_bm, r, nullptr); });
 }
 
 feod_status apply_jvp(feod_ctx* c, const double* u, const double* v, double* jv, double* r, int prec,
                       double p_override = 0.0) {
   if (r) {
     TRY(run_element(c, OP_RESJVP, prec, params(c, u, v, c->d_Y0, c->d_Y1, prec, p_override)));
-    return timed(c, "gather_transpose2", [&] {
-      return launch_gather_t(c->d_toff, c->d_tidx, c->d_Y0, c->d_Y1, prec == 1, c->d_bm, r, jv,
-                             c->lat.N, c->stream);
-    });
+    return timed(c, "gather_transpose2", [&] { return gather_t(c, c->d_Y0, c->d_Y1, prec == 1, c->d_bm, r, jv); });
   }
   TRY(run_element(c, OP_JVP, prec, params(c, u, v, c->d_Y0, nullptr, prec, p_override)));
-  return timed(c, "gather_transpose", [&] {
-    return launch_gather_t(c->d_toff, c->d_tidx, c->d_Y0, nullptr, prec == 1, nullptr, jv, nullptr,
-                           c->lat.N, c->stream);
-  });
+  return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, jv, nullptr); });
 }
 
 // out_dev[0] = sum x*y (y may be null: sum x), deterministic
@@ -547,6 +552,13 @@ feod_status feod_sizes(const feod_ctx* c, int64_t* n_dofs, int64_t* n_elems) {
   if (!c) return fail(nullptr, FEOD_EINVAL, "null context");
   if (n_dofs) *n_dofs = c->lat.N;
   if (n_elems) *n_elems = c->lat.E;
+  return FEOD_OK;
+}
+
+feod_status feod_set_map_mode(feod_ctx* c, int32_t mode) {
+  if (!c) return fail(nullptr, FEOD_EINVAL, "null context");
+  if (mode != FEOD_MAPS_LATTICE && mode != FEOD_MAPS_EXPLICIT) return fail(c, FEOD_EINVAL, "invalid map mode");
+  c->explicit_maps = mode == FEOD_MAPS_EXPLICIT;
   return FEOD_OK;
 }
 
@@ -832,7 +844,8 @@ feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, doub
   const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1};
   const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1};
   *flops = E * (passes[op] * S + NQ3 * (fD[op] + geo));
-  double b = fields[op] * 8.0 * N + 4.0 * E * Ne;  // unique L-vector reads + map
+  double b = fields[op] * 8.0 * N;  // unique L-vector reads
+  if (c->explicit_maps) b += 4.0 * E * Ne;  // stored element-to-DOF map
   if (c->has_rho) b += 8.0 * E;
   if (c->curved) b += 24.0 * (c->nx + 1.0) * (c->ny + 1.0) * (c->nz + 1.0);
   b += outs[op] * ts * E * Ne;

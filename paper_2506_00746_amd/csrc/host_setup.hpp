@@ -27,9 +27,13 @@ struct Lattice {
   int Ne = 0;
   std::vector<int32_t> emap;  // E*Ne, global DOF or -1 on Dirichlet DOFs
   std::vector<int32_t> toff;  // N+1 row offsets of the transposed map
-  std::vector<int32_t> tidx;  // E-vector positions e*Ne+a, ascending within a row
+  std::vector<int32_t> tidx;  // E-vector positions of each DOF's entries, by ascending element
   std::vector<uint8_t> interior;
 };
+
+// Position of entry (element e, local node a + D1 (b + D1 c)) in the output
+// E-vector (layout chosen by FEOD_EVEC_ROWMAJOR: e*Ne + local by default).
+int64_t evec_position(const Lattice& L, int64_t e, int local);
 
 // Returns false (with msg) when a size would overflow 32-bit indices.
 bool make_lattice(int nx, int ny, int nz, int k, Lattice* L, std::string* msg);

@@ -14,7 +14,8 @@ enum : int { OP_RESIDUAL = 0, OP_JVP = 1, OP_RESJVP = 2, OP_ENERGY = 3, OP_GRAD 
 struct ElemParams {
   const double* u;        // L-vector (FP64)
   const double* v;        // second L-vector: JVP direction or adjoint lambda
-  const int32_t* emap;    // E x Ne element-to-DOF map, -1 on Dirichlet DOFs
+  const int32_t* emap;    // E x Ne element-to-DOF map, -1 on Dirichlet DOFs; nullptr:
+                          // computed from the lattice (same map, no memory traffic)
   const double* rho;      // E coefficients or nullptr (all ones)
   const double* verts;    // (nx+1)(ny+1)(nz+1) x 3, curved meshes only
   const void* tab;        // 1D tables in the kernel precision: B, D (nq x D1), w, xi (nq)
@@ -22,12 +23,22 @@ struct ElemParams {
   void* out1;             // second E-vector (residual + JVP)
   const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
+  int32_t k, Lx, Ly, Lz;  // order and node-lattice extents (k n + 1 per direction)
   double hinv[3];         // affine meshes: 1/h per direction
   double det;             // affine meshes: element volume h_x h_y h_z
   double sdet[3];         // affine meshes: det * hinv
   double p, eps2, r, inv_p;
   int32_t powkind;
 };
+
+// Output E-vector layout: 0 (default) = [e][c][b][a], each element's entries
+// contiguous, so the element kernel's writes are whole-element runs; 1 =
+// [ez][ey][c][b][ex][a], element rows contiguous per (c,b).  Measured on the
+// 32^3 Q3 Jacobian apply: 0 is faster (element kernel 37.4 vs 40.1 us, G^T the
+// same 9.4 us).
+#ifndef FEOD_EVEC_ROWMAJOR
+#define FEOD_EVEC_ROWMAJOR 0
+#endif
 
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Renumber them so that XCD j processes one contiguous range of the
@@ -60,6 +71,16 @@ constexpr int kRedBlocks = 1024;  // fixed grid of the two-stage reductions
 hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y0, const void* Y1,
                            bool fp32, const double* bm, double* out0, double* out1, int64_t n,
                            hipStream_t s);
+
+// Structured lattice of the element-to-DOF map, for the computed G^T.
+struct LatticeDims {
+  int32_t nx, ny, nz, k, Lx, Ly, Lz;
+};
+// Same sums as launch_gather_t, in the same (ascending E-vector position)
+// order, with each DOF's element list computed from the lattice.
+hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
+                                   const double* bm, double* out0, double* out1, int64_t n,
+                                   hipStream_t s);
 
 // partial[b] = sum over block b's grid-stride share of x[i]*y[i] (y == nullptr: x[i]).
 hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, double* partial,

@@ -61,6 +61,79 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
   return hipGetLastError();
 }
 
+// Computed transposed map: DOF (I,J,K) of the (k nx+1)(k ny+1)(k nz+1) node
+// lattice lies in element ex = I/k (local a = I%k) and, when I is a multiple
+// of k, also in ex-1 (local a = k); likewise in y and z.  The contributions are
+// summed in ascending element order, which is the order of the explicit map.
+// E-vector layout [ez][ey][c][b][ex][a]: a wavefront of consecutive I reads
+// one contiguous stretch per (element row, c, b).
+template <class TE, bool TWO>
+__global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDims d, const TE* __restrict__ Y0,
+                                                                       const TE* __restrict__ Y1,
+                                                                       const double* __restrict__ bm,
+                                                                       double* __restrict__ out0,
+                                                                       double* __restrict__ out1, int64_t n) {
+  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kVecThreads + threadIdx.x;
+  if (i >= n) return;
+  // n < 2^31 (checked at set-up): 32-bit unsigned index arithmetic
+  const uint32_t iu = (uint32_t)i, t = iu / (uint32_t)d.Lx;
+  const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)(t / (uint32_t)d.Ly), J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
+  double s0 = 0, s1 = 0;
+  if (I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1) {
+    const int k = d.k, D1 = k + 1;
+    // up to two candidate elements per direction: lower (index/k - 1, local k)
+    // when the index is a multiple of k, and upper (index/k, local index%k)
+    const int ix = I / k, iy = J / k, iz = K / k;
+    const bool lx = I - k * ix == 0, ly = J - k * iy == 0, lz = K - k * iz == 0;
+    TE v0[8], v1[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {  // q = tx + 2 ty + 4 tz, ascending element order
+      const int tx = q & 1, ty = (q >> 1) & 1, tz = q >> 2;
+      const bool use = (tx || lx) && (ty || ly) && (tz || lz);
+      const int ex = ix - 1 + tx, ey = iy - 1 + ty, ez = iz - 1 + tz;
+      const int a = I - k * ex, b = J - k * ey, c = K - k * ez;
+#if FEOD_EVEC_ROWMAJOR
+      const uint32_t j = ((((uint32_t)ez * d.ny + ey) * D1 + c) * D1 + b) * (uint32_t)(d.nx * D1) + ex * D1 + a;
+#else
+      const uint32_t j = ((uint32_t)ex + (uint32_t)d.nx * (ey + (uint32_t)d.ny * ez)) * (uint32_t)(D1 * D1 * D1) +
+                         a + D1 * (b + D1 * c);
+#endif
+      v0[q] = use ? Y0[j] : TE(0);
+      if (TWO) v1[q] = use ? Y1[j] : TE(0);
+    }
+    // adding +0 for absent candidates leaves the ordered sum bitwise unchanged
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      s0 += (double)v0[q];
+      if (TWO) s1 += (double)v1[q];
+    }
+    if (bm != nullptr) s0 -= bm[i];
+  }
+  out0[i] = s0;
+  if (TWO) out1[i] = s1;
+}
+
+hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
+                                   const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
+  const int nb = vec_blocks(n);
+  if (fp32) {
+    if (Y1)
+      hipLaunchKernelGGL((gather_t_lattice_kernel<float, true>), dim3(nb), dim3(kVecThreads), 0, s, d,
+                         (const float*)Y0, (const float*)Y1, bm, out0, out1, n);
+    else
+      hipLaunchKernelGGL((gather_t_lattice_kernel<float, false>), dim3(nb), dim3(kVecThreads), 0, s, d,
+                         (const float*)Y0, nullptr, bm, out0, nullptr, n);
+  } else {
+    if (Y1)
+      hipLaunchKernelGGL((gather_t_lattice_kernel<double, true>), dim3(nb), dim3(kVecThreads), 0, s, d,
+                         (const double*)Y0, (const double*)Y1, bm, out0, out1, n);
+    else
+      hipLaunchKernelGGL((gather_t_lattice_kernel<double, false>), dim3(nb), dim3(kVecThreads), 0, s, d,
+                         (const double*)Y0, nullptr, bm, out0, nullptr, n);
+  }
+  return hipGetLastError();
+}
+
 // Fixed-shape block reduction: wavefront shuffles, then the 4 wave sums in order.
 __device__ __forceinline__ double block_sum(double v) {
   __shared__ double ws[kVecThreads / 64];

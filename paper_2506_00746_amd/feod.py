@@ -73,6 +73,7 @@ _SIGS = {
     "feod_bind_workspace": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "feod_sizes": (ctypes.c_int, [_P, _P, _P]),
     "feod_set_stream": (ctypes.c_int, [_P, _P]),
+    "feod_set_map_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P]),
@@ -208,6 +209,10 @@ class Problem:
 
     def _sync_stream(self):
         lib().feod_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
+
+    def set_map_mode(self, mode: str):
+        """'lattice' (computed G/G^T, default) or 'explicit' (stored maps)."""
+        _check(lib().feod_set_map_mode(self._ctx, {"lattice": 0, "explicit": 1}[mode]), self._ctx)
 
     # -- operators (Eq. (1), Eq. (2)) -------------------------------------
     def residual(self, u, out=None, prec="fp64"):

@@ -42,7 +42,8 @@ def test_maps_match_oracle(shape, k, nq):
     d = Discretisation(*shape, k, nq, 3.0, 1e-2)
     expect = np.where(d.mask[d.elem_dofs] > 0, d.elem_dofs, -1)
     assert np.array_equal(h.emap, expect)
-    # transposed map: row i lists the E-vector positions of DOF i, ascending
+    # transposed map: row i lists the E-vector positions (e * Ne + local) of
+    # DOF i by ascending element
     flat = expect.ravel()
     for i in range(d.N):
         row = h.tidx[h.toff[i]:h.toff[i + 1]]

@@ -133,3 +133,18 @@ def test_full_size_sampled_parity(name):
           f"{relerr(rm[dofs], jv[dofs]):.2e}")
     del prob
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("w", [SMALL[1], SMALL[4], SMALL[6]], ids=["q2", "q3-curved", "q7-curved"])
+def test_lattice_and_explicit_maps_bitwise_equal(w):
+    announce("map modes", w)
+    prob, ora, inp = setup(w, oracle=False)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    outs = {}
+    for mode in ("lattice", "explicit"):
+        prob.set_map_mode(mode)
+        r, jv = prob.residual_and_jvp(u, v)
+        rm = prob.residual(u, prec="mixed")
+        outs[mode] = [host(r), host(jv), host(rm), host(prob.jacobian_apply(u, v))]
+    for a, b in zip(outs["lattice"], outs["explicit"]):
+        assert np.array_equal(a, b)
