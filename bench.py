@@ -9,8 +9,10 @@ Also reported on the same JSON line (each timed separately, none of it part
 of ``value``): the mixed-precision Jacobian apply, the residual, the fused
 residual + Jacobian apply, the same applies on the other workloads, the
 Newton-CG and adjoint-gradient times on the design workload, the roofline of
-the dominant kernel from hipEvents the library records around every launch
-on its stream, and the CPU oracle timed on a bounded sample.
+the dominant (element) kernel, whose duration is timed with events over
+back-to-back launches of the element stage alone on the library's stream,
+its HBM traffic from the committed rocprofv3 summary (when measured on the
+current kernel sources), and the CPU oracle timed on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
        [--no-extras] [--no-cpu-baseline] [--calibrate-copy]
@@ -63,9 +65,24 @@ def kernel_profile(prob, fn, steps):
     return {k: {"launches": n, "avg_ms": ms / n} for k, (n, ms) in stats.items()}
 
 
-def roofline(prob, op, prec, stats, kernel):
+def element_kernel_ms(prob, u, v, op, prec, steps, warmup):
+    """Average duration of the element kernel alone: back-to-back launches
+    timed with events on the stream the library launches on."""
+    return timed_loop(lambda: prob.element_vectors(op, u, v, prec=prec), steps, warmup)
+
+
+def stored_traffic(workload, kernel):
+    """HBM bytes per launch from the committed rocprofv3 summary, if it was
+    measured on the current kernel sources (else None)."""
+    from paper_2506_00746_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}.md")
+    b, sha = profiling.read_traffic(path)
+    return b if (b is not None and sha == profiling.kernel_source_sha256()) else None
+
+
+def roofline(prob, op, prec, stats, kernel, kernel_ms=None):
     bytes_, flops = prob.kernel_cost(op, prec)
-    avg_s = stats[kernel]["avg_ms"] * 1e-3
+    avg_s = (kernel_ms if kernel_ms is not None else stats[kernel]["avg_ms"]) * 1e-3
     gbs = bytes_ / avg_s / 1e9
     tfs = flops / avg_s / 1e12
     peak_alu = FP64_PEAK_TFS if prec == "fp64" else FP32_PEAK_TFS
@@ -99,7 +116,8 @@ def apply_rows(prob, u, v, w, args, only=None):
             continue
         t = timed_loop(fn, args.steps, args.warmup)
         st = kernel_profile(prob, fn, min(args.steps, 50))
-        rl = roofline(prob, op, prec, st, kern)
+        k_ms = element_kernel_ms(prob, u, v, op, prec, args.steps, args.warmup)
+        rl = roofline(prob, op, prec, st, kern, kernel_ms=k_ms)
         gt = st.get("gather_transpose", st.get("gather_transpose2", {"avg_ms": 0.0}))
         out[name] = {"GDOF/s": N / (t * 1e-3) / 1e9, "us_per_apply": t * 1e3, "kernel_us": rl["avg_us"],
                      "kernel_bound": rl["bound"], "kernel_frac": rl["frac"],
@@ -204,8 +222,11 @@ def main():
     ms = timed_loop(jvp64, args.steps, args.warmup)
     value = N / (ms * 1e-3) / 1e9
     stats = kernel_profile(prob, jvp64, min(args.steps, 50))
-    roof = roofline(prob, "jvp", "fp64", stats, "element_jvp_f64")
-    log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s; kernels {stats}")
+    k_ms = element_kernel_ms(prob, u, v, "jvp", "fp64", args.steps, args.warmup)
+    roof = roofline(prob, "jvp", "fp64", stats, "element_jvp_f64", kernel_ms=k_ms)
+    roof["traffic"] = stored_traffic(w.name, "element_jvp_f64")
+    log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s; element kernel {k_ms * 1e3:.2f} us "
+        f"back-to-back; per-launch events {stats}")
 
     rows = {w.name: {"jvp_fp64": {"GDOF/s": value, "us_per_apply": ms * 1e3, "kernel_us": roof["avg_us"],
                                   "kernel_bound": roof["bound"], "kernel_frac": roof["frac"]}}}

@@ -161,6 +161,13 @@ feod_status feod_residual(feod_ctx* ctx, const double* u, double* r, feod_prec p
 feod_status feod_jacobian_apply(feod_ctx* ctx, const double* u, const double* v,
                                 double* jv, double* r_or_null, feod_prec prec);
 
+/* The element stage alone, G -> B -> D -> B^T of Eq. (1)/(2), written into
+ * the context's internal E-vector(s) (no G^T): op 0 residual, 1 Jacobian
+ * action, 2 both.  For timing the element kernel on its own; u, v: device,
+ * length N (v ignored for op 0). */
+feod_status feod_element_vectors(feod_ctx* ctx, int32_t op, const double* u, const double* v,
+                                 feod_prec prec);
+
 /* Energy E(u) = sum_e rho_e int_e (1/p)(eps^2+|grad Mu|^2)^(p/2) - b^T M u,
  * whose gradient is R (line-search merit function).  e_dev: device, 1 double. */
 feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev);

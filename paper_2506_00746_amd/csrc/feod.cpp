@@ -598,6 +598,17 @@ feod_status feod_jacobian_apply(feod_ctx* c, const double* u, const double* v, d
   return apply_jvp(c, u, v, jv, r, prec == FEOD_MIXED);
 }
 
+feod_status feod_element_vectors(feod_ctx* c, int32_t op, const double* u, const double* v, feod_prec prec) {
+  TRY(need_bound(c));
+  TRY(check_prec(c, prec));
+  TRY(check_vec(c, u, "u"));
+  if (op < 0 || op > 2) return fail(c, FEOD_EINVAL, "op must be 0, 1 or 2");
+  if (op > 0) TRY(check_vec(c, v, "v"));
+  const int pr = prec == FEOD_MIXED;
+  const int kop = op == 0 ? OP_RESIDUAL : (op == 1 ? OP_JVP : OP_RESJVP);
+  return run_element(c, kop, pr, params(c, u, op > 0 ? v : nullptr, c->d_Y0, c->d_Y1, pr));
+}
+
 feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev) {
   TRY(need_bound(c));
   TRY(check_vec(c, u, "u"));
@@ -830,20 +841,40 @@ feod_status feod_profile_read(feod_ctx* c, feod_kernel_stat* stats, int32_t max,
   return FEOD_OK;
 }
 
+// Floating-point operations of the pointwise operator D per quadrature point,
+// counted from the kernel source (FMA = 2, mul/add = 1, reciprocal square
+// root / division / pow = 1 each; a refined reciprocal square root is 1 + 8).
+static double pointwise_flops(int op, int pk, bool curved) {
+  // a^r: scalar and dual (value + tangent), by exponent kind
+  const double apow_s[5] = {0, 20, 10, 0, 3};
+  const double apow_d[5] = {0, 24, 12, 0, 6};
+  double f = 0;
+  switch (op) {
+    case OP_RESIDUAL: f = 20 + apow_s[pk]; break;  // w, g, a, F, pull-back
+    case OP_JVP: f = 38 + apow_d[pk]; break;       // dual a and F, tangent pull-back
+    case OP_RESJVP: f = 44 + apow_d[pk]; break;    // + value pull-back
+    case OP_ENERGY: f = 16 + apow_s[pk]; break;    // a, W = a a^r / p, weight
+    case OP_GRAD: f = 22 + apow_s[pk]; break;      // a^r g_u . g_lambda, weight
+    default: f = 0;
+  }
+  if (curved) {  // Jacobian, adjugate, determinant, transforms (per-line set-up amortised)
+    const double geo[OP_COUNT] = {78, 93, 105, 66, 81, 0};
+    f += geo[op];
+  }
+  return f;
+}
+
 feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, double* bytes, double* flops) {
-  if (!c || !bytes || !flops || op < 0 || op >= OP_COUNT) return fail(nullptr, FEOD_EINVAL, "invalid argument");
+  if (!c || !bytes || !flops || op < 0 || op >= OP_DIAG) return fail(nullptr, FEOD_EINVAL, "invalid argument");
   const double E = (double)c->lat.E, N = (double)c->lat.N, Ne = c->Ne, nq = c->nq, D1 = c->D1;
   const double NQ3 = (double)c->NQ3;
   const double ts = prec == FEOD_MIXED ? 4.0 : 8.0;
   // one sum-factorised gradient pass (B or B^T) per field, FMA = 2
   const double S = 4 * nq * D1 * D1 * D1 + 6 * nq * nq * D1 * D1 + 6 * nq * nq * nq * D1;
-  // pointwise operation counts per quadrature point (see DESIGN)
-  const double geo = c->curved ? 120.0 : 0.0;
-  const double fD[OP_COUNT] = {45.0, 93.0, 111.0, 22.0, 47.0, 0.0};
   const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0};
   const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1};
   const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1};
-  *flops = E * (passes[op] * S + NQ3 * (fD[op] + geo));
+  *flops = E * (passes[op] * S + NQ3 * pointwise_flops(op, pow_kind(c->p), c->curved));
   double b = fields[op] * 8.0 * N;  // unique L-vector reads
   if (c->explicit_maps) b += 4.0 * E * Ne;  // stored element-to-DOF map
   if (c->has_rho) b += 8.0 * E;

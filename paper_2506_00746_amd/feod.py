@@ -77,6 +77,7 @@ _SIGS = {
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P]),
+    "feod_element_vectors": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int]),
     "feod_jacobian_diagonal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_newton_solve": (ctypes.c_int, [_P, _P, _P, _P]),
     "feod_adjoint_gradient": (ctypes.c_int, [_P, _P, _P, _P, _P, _P, _P]),
@@ -237,6 +238,13 @@ class Problem:
         r = self._vec()
         jv = self.jacobian_apply(u, v, residual_out=r, prec=prec)
         return r, jv
+
+    def element_vectors(self, op: str, u, v=None, prec="fp64"):
+        """Run only the element kernel (G, B, D, B^T) into the internal E-vector."""
+        self._sync_stream()
+        vp = None if v is None else _dptr(v, self.n_dofs, "v")
+        _check(lib().feod_element_vectors(self._ctx, {"residual": 0, "jvp": 1, "resjvp": 2}[op],
+                                          _dptr(u, self.n_dofs, "u"), vp, PREC[prec]), self._ctx)
 
     def energy(self, u):
         e = torch.empty(1, dtype=torch.float64, device=self.device)

@@ -104,3 +104,13 @@ def test_unbound_context_and_null_args():
     finally:
         L.feod_destroy(ctx)
     assert L.feod_destroy(None) == 0
+
+
+def test_profile_summary_parser_and_source_hash(tmp_path):
+    from paper_2506_00746_amd import profiling
+    sha = profiling.kernel_source_sha256()
+    assert len(sha) == 64
+    p = tmp_path / "x.md"
+    p.write_text(f"# x\n\ntraffic_bytes_per_launch: 3.2e+07\nkernel_source_sha256: {sha}\n")
+    assert profiling.read_traffic(str(p)) == (3.2e7, sha)
+    assert profiling.read_traffic(str(tmp_path / "missing.md")) == (None, None)
