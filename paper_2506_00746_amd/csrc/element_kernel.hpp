@@ -69,13 +69,13 @@ struct Unroll {
 // LDS layout.  The x-pass buffer is [c][qx][b]; when D1 is a multiple of 8
 // its qx stride is padded by one scalar, otherwise the NQ distinct qx columns
 // phase C reads at once would fall on only two LDS banks.
-template <int D1, int NQ, int F, int O>
+template <int D1, int NQ, int XB, int HF>
 struct Lds {
   static constexpr int XQ = D1 % 8 ? D1 : D1 + 1;  // qx stride
   static constexpr int XC = NQ * XQ;              // c stride
   static constexpr int XS = D1 * XC;              // one x-pass output block [c][qx][b]
-  static constexpr int X = (F > O ? F : O) * 2 * XS;  // x-pass output of F fields (reused for K)
-  static constexpr int H = O * 3 * D1 * NQ * NQ;  // z-back output [o][d][c][qy][qx]
+  static constexpr int X = XB * XS;               // XB blocks: x-pass outputs, later y-back outputs
+  static constexpr int H = HF * D1 * NQ * NQ;     // HF z-back fields [h][c][qy][qx]
   static constexpr int per_elem = X + H + 24;
 };
 
@@ -191,7 +191,12 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   constexpr bool SEQ = C::SEQ && F == 2;
   static_assert(!SEQ || EB * NQ2 <= NT, "sequential fields need one phase-C line per thread");
   constexpr int FX = SEQ ? 1 : F;  // fields resident in the x-pass buffer at once
-  using L = Lds<D1, NQ, FX, O>;
+  constexpr bool DIAG = OP == OP_DIAG;
+  // z-back fields: 3 per output (x, y, z flux components); the diagonal has 6
+  // (the symmetric tensor terms); y-back blocks: 2 per output, 3 for the diagonal
+  constexpr int HF = DIAG ? 6 : 3 * O;
+  constexpr int KB = DIAG ? 3 : 2 * O;
+  using L = Lds<D1, NQ, (2 * FX > KB ? 2 * FX : KB), HF>;
   __shared__ T smem[EB * L::per_elem];
   __shared__ T sB[NQ * L::XQ], sD[NQ * L::XQ];  // table rows, same padded stride
   T* Xs = smem;                 // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
@@ -302,6 +307,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       }
     }
     double part = 0;  // energy / gradient partial over the column
+    T cd[DIAG ? 6 : 1][NQ];  // diagonal: the six symmetric tensor terms per point
 #pragma unroll
     for (int qz = 0; qz < NQ; ++qz) {
       const T w3 = wxy * tb.w[qz];
@@ -343,7 +349,45 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
         }
       }
       T Fo[O][3];
-      if constexpr (OP == OP_RESIDUAL) {
+      if constexpr (DIAG) {
+        // J_D by forward mode along each physical direction: Tm[a][d] = dF_a/dg_d
+        T Tm[3][3];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          dual<T> gd[3], Fd[3];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) gd[a] = {gu[a], a == d ? T(1) : T(0)};
+          flux<PK, dual<T>, T>(gd, eps2, r, Fd);
+#pragma unroll
+          for (int a = 0; a < 3; ++a) Tm[a][d] = Fd[a].d;
+        }
+        // reference-space tensor Chat = rho w det Jg^{-1} Tm Jg^{-T}
+        T Ch[3][3];
+        const T s = rho * w3;
+        if (CURVED) {
+          const T sd = s / det;
+          T AT[3][3];  // adj Tm
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) AT[i][j] = adj[i][0] * Tm[0][j] + adj[i][1] * Tm[1][j] + adj[i][2] * Tm[2][j];
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Ch[i][j] = sd * (AT[i][0] * adj[j][0] + AT[i][1] * adj[j][1] + AT[i][2] * adj[j][2]);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Ch[i][j] = s * det * (T)P.hinv[i] * (T)P.hinv[j] * Tm[i][j];
+        }
+        cd[0][qz] = Ch[0][0];
+        cd[1][qz] = Ch[1][1];
+        cd[2][qz] = Ch[2][2];
+        cd[3][qz] = Ch[0][1] + Ch[1][0];
+        cd[4][qz] = Ch[0][2] + Ch[2][0];
+        cd[5][qz] = Ch[1][2] + Ch[2][1];
+      } else if constexpr (OP == OP_RESIDUAL) {
         flux<PK, T, T>(gu, eps2, r, Fo[0]);
       } else if constexpr (OP == OP_JVP || OP == OP_RESJVP) {
         dual<T> gd[3], Fd[3];
@@ -364,7 +408,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
         density<PK, T>(gu, eps2, r, inv_p, &W, &cf);
         part -= (double)(w3 * det * cf * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
       }
-      if constexpr (!REDUCE) {
+      if constexpr (!REDUCE && !DIAG) {
         // reference flux Fhat = rho w det Jg^{-1} F = rho w adj F (stored over g)
         const T s = rho * w3;
 #pragma unroll
@@ -381,6 +425,26 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
     }
     if constexpr (REDUCE) {
       Hs[l] = (T)part;
+    } else if constexpr (DIAG) {
+      // z factors of the six terms: B^2 (00, 11, 01), D^2 (22), B D (02, 12)
+      T* h = Hs + el * L::H + qxy;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
+      for (int c = 0; c < D1; ++c) {
+        T s[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int qz = 0; qz < NQ; ++qz) {
+          const T bz = tb.B[qz * D1 + c], dz = tb.D[qz * D1 + c];
+          const T bb = bz * bz, dd = dz * dz, bd = bz * dz;
+          s[0] += bb * cd[0][qz];
+          s[1] += bb * cd[1][qz];
+          s[2] += dd * cd[2][qz];
+          s[3] += bb * cd[3][qz];
+          s[4] += bd * cd[4][qz];
+          s[5] += bd * cd[5][qz];
+        }
+#pragma unroll
+        for (int t = 0; t < 6; ++t) h[(t * D1 + c) * NQ2] = s[t];
+      }
     } else {
       // z-back: H0[c] = sum_qz B Fx, H1 = sum_qz B Fy, H2 = sum_qz D Fz
 #pragma unroll
@@ -418,6 +482,35 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   for (int l = tid; l < EB * D1 * NQ; l += NT) {
     const int el = l / (D1 * NQ), rem = l - el * (D1 * NQ);
     const int c = rem / NQ, qx = rem - c * NQ;
+    if constexpr (DIAG) {
+      // group by x factor: K_D2 (term 00), K_B2 (11, 22, 12), K_DB (01, 02)
+      const T* h = Hs + el * L::H + c * NQ2 + qx;
+      T hv[6][NQ];
+#pragma unroll
+      for (int t = 0; t < 6; ++t)
+#pragma unroll
+        for (int qy = 0; qy < NQ; ++qy) hv[t][qy] = h[t * D1 * NQ2 + qy * NQ];
+      T* k = Xs + el * L::X + (c * NQ + qx) * L::XQ;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
+      for (int b = 0; b < D1; ++b) {
+        T kd2 = 0, kb2 = 0, kdb = 0;
+#pragma unroll
+        for (int qy = 0; qy < NQ; ++qy) {
+          const T by = tb.B[qy * D1 + b], dy = tb.D[qy * D1 + b];
+          const T bb = by * by, dd = dy * dy, bd = by * dy;
+          kd2 += bb * hv[0][qy];
+          kb2 += dd * hv[1][qy];
+          kb2 += bb * hv[2][qy];
+          kb2 += bd * hv[5][qy];
+          kdb += bd * hv[3][qy];
+          kdb += bb * hv[4][qy];
+        }
+        k[b] = kd2;
+        k[L::XS + b] = kb2;
+        k[2 * L::XS + b] = kdb;
+      }
+      continue;
+    }
 #pragma unroll
     for (int o = 0; o < O; ++o) {
       const T* h = Hs + el * L::H + o * 3 * D1 * NQ2 + c * NQ2 + qx;
@@ -460,6 +553,30 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
     if (el >= n_valid) continue;
     const int64_t pos = (int64_t)(e0 + el) * Ne + cb * D1;
 #endif
+    if constexpr (DIAG) {
+      const T* k = Xs + el * L::X + c * L::XC + b;
+      T kd2[NQ], kb2[NQ], kdb[NQ];
+#pragma unroll
+      for (int qx = 0; qx < NQ; ++qx) {
+        kd2[qx] = k[qx * L::XQ];
+        kb2[qx] = k[L::XS + qx * L::XQ];
+        kdb[qx] = k[2 * L::XS + qx * L::XQ];
+      }
+      T* out = static_cast<T*>(P.out0) + pos;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
+      for (int a = 0; a < D1; ++a) {
+        T sacc = 0;
+#pragma unroll
+        for (int qx = 0; qx < NQ; ++qx) {
+          const T bx = tb.B[qx * D1 + a], dx = tb.D[qx * D1 + a];
+          sacc += dx * dx * kd2[qx];
+          sacc += bx * bx * kb2[qx];
+          sacc += bx * dx * kdb[qx];
+        }
+        out[a] = sacc;
+      }
+      continue;
+    }
 #pragma unroll
     for (int o = 0; o < O; ++o) {
       const T* k = Xs + el * L::X + o * 2 * L::XS + c * L::XC + b;
@@ -521,6 +638,7 @@ Tab<D1, NQ, T> make_tab(const double* h) {
     t.op[OP_RESJVP][CURVED][PK] = &launch_##DD##_##QQ<T, OP_RESJVP, CURVED, PK>;                  \
     t.op[OP_ENERGY][CURVED][PK] = &launch_##DD##_##QQ<T, OP_ENERGY, CURVED, PK>;                  \
     t.op[OP_GRAD][CURVED][PK] = &launch_##DD##_##QQ<T, OP_GRAD, CURVED, PK>;                      \
+    t.op[OP_DIAG][CURVED][PK] = &launch_##DD##_##QQ<T, OP_DIAG, CURVED, PK>;                      \
   }                                                                                               \
   template <class T, bool CURVED>                                                                 \
   static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                       \

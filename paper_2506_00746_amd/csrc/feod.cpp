@@ -273,6 +273,18 @@ feod_status apply_jvp(feod_ctx* c, const double* u, const double* v, double* jv,
   return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, jv, nullptr); });
 }
 
+// diag(J(u)) = M G^T (element diagonals), boundary rows 0
+feod_status apply_diagonal(feod_ctx* c, const double* u, double* diag, int prec) {
+  TRY(run_element(c, OP_DIAG, prec, params(c, u, nullptr, c->d_Y0, nullptr, prec)));
+  return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, diag, nullptr); });
+}
+
+// dinv = 1 / diag(J(u)) on interior DOFs, 0 on Dirichlet DOFs (Jacobi preconditioner)
+feod_status jacobi(feod_ctx* c, const double* u, double* dinv, double* tmp) {
+  TRY(apply_diagonal(c, u, tmp, 0));
+  return timed(c, "invert_diag", [&] { return launch_invert_diag(dinv, tmp, c->lat.N, c->stream); });
+}
+
 // out_dev[0] = sum x*y (y may be null: sum x), deterministic
 feod_status dot(feod_ctx* c, const double* x, const double* y, int64_t n, double* out_dev,
                 double sign = 1.0, const double* add = nullptr) {
@@ -392,7 +404,6 @@ feod_status validate_opts(feod_ctx* c, const feod_solver_opts& o) {
   if (!(o.rtol > 0) || !(o.cg_rtol_floor > 0) || o.max_newton < 0 || o.max_cg < 1 || o.max_ls < 0 ||
       o.check_every < 1 || (o.prec != FEOD_FP64 && o.prec != FEOD_MIXED))
     return fail(c, FEOD_EINVAL, "invalid solver options");
-  if (o.jacobi) return fail(c, FEOD_EUNSUPPORTED, "Jacobi preconditioning is not built");
   return FEOD_OK;
 }
 
@@ -619,10 +630,12 @@ feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev) {
 
 feod_status feod_jacobian_diagonal(feod_ctx* c, const double* u, double* diag, feod_prec prec) {
   TRY(need_bound(c));
-  (void)u;
-  (void)diag;
-  (void)prec;
-  return fail(c, FEOD_EUNSUPPORTED, "Jacobian diagonal is not built");
+  TRY(check_prec(c, prec));
+  TRY(check_vec(c, u, "u"));
+  TRY(check_vec(c, diag, "diag"));
+  const size_t nb = (size_t)c->lat.N * 8;
+  if (overlap(u, nb, diag, nb)) return fail(c, FEOD_EINVAL, "diag overlaps u");
+  return apply_diagonal(c, u, diag, prec == FEOD_MIXED);
 }
 
 feod_status feod_grad_rho(feod_ctx* c, const double* u, const double* lam, double* grad, feod_prec prec) {
@@ -705,7 +718,12 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
     if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(rhs, -1.0, R, 0.0, nullptr, N, c->stream); });
         s != FEOD_OK)
       return finish(s);
-    if (feod_status s = cg(c, u, rhs, du, eta, o.max_cg, o.check_every, prec, nullptr, &cr); s != FEOD_OK)
+    const double* dinv = nullptr;
+    if (o.jacobi) {
+      if (feod_status s = jacobi(c, u, c->d_vec[V_DINV], ut); s != FEOD_OK) return finish(s);
+      dinv = c->d_vec[V_DINV];
+    }
+    if (feod_status s = cg(c, u, rhs, du, eta, o.max_cg, o.check_every, prec, dinv, &cr); s != FEOD_OK)
       return finish(s);
     rep.cg_iters_total += cr.iters;
     // Armijo backtracking on the energy
@@ -762,8 +780,13 @@ feod_status feod_adjoint_gradient(feod_ctx* c, const double* u, const double* g_
       s != FEOD_OK)
     return finish(s);
   CgResult cr;
+  const double* dinv = nullptr;
+  if (o.jacobi) {
+    if (feod_status s = jacobi(c, u, c->d_vec[V_DINV], c->d_vec[V_AUX2]); s != FEOD_OK) return finish(s);
+    dinv = c->d_vec[V_DINV];
+  }
   if (o.prec == FEOD_FP64) {
-    if (feod_status s = cg(c, u, rhs, lam, o.rtol, o.max_cg, o.check_every, 0, nullptr, &cr); s != FEOD_OK)
+    if (feod_status s = cg(c, u, rhs, lam, o.rtol, o.max_cg, o.check_every, 0, dinv, &cr); s != FEOD_OK)
       return finish(s);
     rep.cg_iters_total = cr.iters;
     rep.ref_norm = cr.bnorm;
@@ -795,7 +818,7 @@ feod_status feod_adjoint_gradient(feod_ctx* c, const double* u, const double* g_
       if (rn <= o.rtol * rep.ref_norm) break;
       if (k >= 50) return finish(fail(c, FEOD_ENOCONV, "iterative refinement did not converge"));
       const double inner = std::max(1e-5, std::min(1e-3, o.rtol * rep.ref_norm / rn));
-      if (feod_status s = cg(c, u, res, d, inner, o.max_cg, o.check_every, 1, nullptr, &cr); s != FEOD_OK)
+      if (feod_status s = cg(c, u, res, d, inner, o.max_cg, o.check_every, 1, dinv, &cr); s != FEOD_OK)
         return finish(s);
       rep.cg_iters_total += cr.iters;
       if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(lam, 1.0, lam, 1.0, d, N, c->stream); });

@@ -148,3 +148,15 @@ def test_lattice_and_explicit_maps_bitwise_equal(w):
         outs[mode] = [host(r), host(jv), host(rm), host(prob.jacobian_apply(u, v))]
     for a, b in zip(outs["lattice"], outs["explicit"]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("w", [SMALL[0], SMALL[2], SMALL[3], SMALL[4], SMALL[5], SMALL[6], SMALL[8]],
+                         ids=["c1", "q2-curved", "q3-p4", "q3-curved", "q4", "q7-curved", "q2-generic"])
+def test_jacobian_diagonal_matches_assembled_oracle(w):
+    announce("diagonal", w)
+    prob, ora, inp = setup(w)
+    d = host(prob.jacobian_diagonal(dev(inp["u"])))
+    d_o = ora.jacobian(inp["u"]).diagonal()
+    assert relerr(d, d_o) <= 1e-12
+    dm = host(prob.jacobian_diagonal(dev(inp["u"]), prec="mixed"))
+    assert relerr(dm, d_o) <= 1e-5

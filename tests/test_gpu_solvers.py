@@ -80,3 +80,21 @@ def test_design_solve_autograd_vs_finite_differences_c4():
         worst = max(worst, abs(fd - grad[e]) / abs(grad[e]))
     print("worst relative FD mismatch over 20 elements:", worst)
     assert worst <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_jacobi_preconditioned_newton_and_adjoint(prec):
+    w = Workload("pcg", 6, 5, 4, 3, 5, 4.0, 1e-3, 33, perturb=True, rho=True)
+    announce("jacobi pcg", w, prec)
+    prob, ora, _ = setup(w)
+    u1, rep1 = prob.newton_solve(rtol=1e-12, prec=prec)
+    u2, rep2 = prob.newton_solve(rtol=1e-12, prec=prec, jacobi=1)
+    print("CG iterations plain", rep1["cg_iters_total"], "jacobi", rep2["cg_iters_total"])
+    assert rep2["status"] == 0 and rep2["res_final"] <= 1e-12 * rep2["ref_norm"]
+    assert relerr(host(u2), host(u1)) <= 1e-10
+    u_o, _ = newton(ora, tol=1e-13)
+    assert relerr(host(u2), u_o) <= 1e-10
+    b = dev(ora.b)
+    g1, _, r1 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec)
+    g2, _, r2 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec, jacobi=1)
+    assert relerr(host(g2), host(g1)) <= 1e-9
