@@ -158,6 +158,41 @@ def solve_rows(feod, WORKLOADS, make_inputs, dev):
     return out
 
 
+def tangent_flops_per_element(k, nq):
+    """Algorithmic FLOPs of one element tangent matrix (Eq. 3) as the kernel
+    computes it: dense reference gradients (12 nq^3 (k+1)^3), the pointwise
+    tangent by three dual evaluations plus transform (~150 per point), and the
+    sum-factorised B^T Chat B over 9 tensor terms, 3 FLOP per multiply-add
+    with a product table: 27 (nq^3 D1^2 + nq^2 D1^4 + nq D1^6)."""
+    d1 = k + 1
+    return (12 * nq ** 3 * d1 ** 3 + 150 * nq ** 3
+            + 27 * (nq ** 3 * d1 ** 2 + nq ** 2 * d1 ** 4 + nq * d1 ** 6))
+
+
+def tangent_rows(feod, WORKLOADS, make_inputs, dev, args):
+    """Element tangent matrices K_e = B^T J_D B (Eq. 3) for every element."""
+    import torch
+    out = {}
+    for name in ("c4", "c2"):
+        w = WORKLOADS[name]
+        ii = make_inputs(w)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=ii["vertices"], rho=ii["rho"],
+                          device=dev)
+        u = torch.as_tensor(ii["u"], device=dev)
+        ne = (w.k + 1) ** 3
+        Ke = torch.empty((w.n_elems, ne, ne), dtype=torch.float64, device=dev)
+        ms = timed_loop(lambda: pb.element_tangents(u, out=Ke), max(3, args.steps // 10), 2)
+        flops = tangent_flops_per_element(w.k, w.nq) * w.n_elems
+        bytes_ = Ke.numel() * 8 + 8 * w.n_dofs
+        out[name] = {"ms_per_launch": ms, "ns_per_element": ms * 1e6 / w.n_elems,
+                     "TFLOP/s": flops / (ms * 1e-3) / 1e12, "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS,
+                     "GB/s": bytes_ / (ms * 1e-3) / 1e9, "matrix_entries": Ke.numel()}
+        log(f"[bench] element tangents {name}: {out[name]}")
+        del pb, u, Ke
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, inp, budget_s=12.0):
     """The oracle's Jacobian apply on the same workload, timed on host cores."""
     import threadpoolctl
@@ -249,6 +284,7 @@ def main():
             del pb, uu, vv
             torch.cuda.empty_cache()
         rows["solves"] = solve_rows(feod, WORKLOADS, make_inputs, dev)
+        rows["element_tangents"] = tangent_rows(feod, WORKLOADS, make_inputs, dev, args)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -168,6 +168,15 @@ feod_status feod_jacobian_apply(feod_ctx* ctx, const double* u, const double* v,
 feod_status feod_element_vectors(feod_ctx* ctx, int32_t op, const double* u, const double* v,
                                  feod_prec prec);
 
+/* Element tangent matrices (Eq. 3): K_e = d r_e / d u_e = B^T J_D(u_q) B for
+ * elements first .. first+count-1, evaluated at the element values of M u,
+ * with J_D from forward-mode dual numbers at each quadrature point and B^T J_D B
+ * contracted by sum factorisation.  Ke: device, count * (k+1)^6 doubles, one
+ * row-major (k+1)^3 x (k+1)^3 matrix per element in local node order
+ * a + (k+1)(b + (k+1) c).  FP64; FEOD_EUNSUPPORTED for k > 4. */
+feod_status feod_element_tangents(feod_ctx* ctx, const double* u, int64_t first, int64_t count,
+                                  double* Ke);
+
 /* Energy E(u) = sum_e rho_e int_e (1/p)(eps^2+|grad Mu|^2)^(p/2) - b^T M u,
  * whose gradient is R (line-search merit function).  e_dev: device, 1 double. */
 feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev);

@@ -309,16 +309,21 @@ class Discretisation:
             out += self.assemble((self.w[None, :] * detJ * fq) @ self.Bval, ch)
         return out
 
+    def element_tangents(self, u, elems):
+        """Eq. (3): K_e = B^T J_D B = sum_q Bgrad^T (rho w detJ Jinv (dF/dg) Jinv^T) Bgrad
+        at the element values of M u, shape (ne, Ne, Ne), local numbering."""
+        _, detJ, Jinv, _ = self.geometry(elems)
+        g = physical_gradient(Jinv, self.ref_gradient(self.gather(u, elems)))
+        T = tangent_matrix(g, self.p, self.eps)
+        C = np.einsum("eqij,eqjk,eqlk->eqil", Jinv, T, Jinv)
+        C *= (self.rho[elems][:, None] * self.w[None, :] * detJ)[..., None, None]
+        return np.einsum("iqa,eqij,jqb->eab", self.Bgrad, C, self.Bgrad)
+
     def jacobian(self, u):
         """Eq. (3) per element, assembled: M J_A(M u) M as a CSR matrix."""
         rows, cols, vals = [], [], []
         for ch in self._chunks(np.arange(self.E)):
-            _, detJ, Jinv, _ = self.geometry(ch)
-            g = physical_gradient(Jinv, self.ref_gradient(self.gather(u, ch)))
-            T = tangent_matrix(g, self.p, self.eps)
-            C = np.einsum("eqij,eqjk,eqlk->eqil", Jinv, T, Jinv)
-            C *= (self.rho[ch][:, None] * self.w[None, :] * detJ)[..., None, None]
-            Ke = np.einsum("iqa,eqij,jqb->eab", self.Bgrad, C, self.Bgrad)
+            Ke = self.element_tangents(u, ch)
             d = self.elem_dofs[ch]
             rows.append(np.repeat(d, self.Ne, axis=1).ravel())
             cols.append(np.tile(d, (1, self.Ne)).ravel())

@@ -619,7 +619,9 @@ Tab<D1, NQ, T> make_tab(const double* h) {
 
 // Instantiate every operation, precision, geometry and exponent kind for one
 // (D1, NQ) and register the launchers in the dispatch table.
-#define FEOD_INSTANTIATE(DD, QQ)                                                                  \
+inline void no_tangents(ElemLaunchers&) {}
+
+#define FEOD_INSTANTIATE(DD, QQ, TANGENTS)                                                        \
   template <class T, int OP, bool CURVED, int PK>                                                 \
   static hipError_t launch_##DD##_##QQ(const ElemParams& P, hipStream_t s) {                      \
     constexpr int EB = Config<DD, QQ, T>::EB;                                                     \
@@ -658,6 +660,7 @@ Tab<D1, NQ, T> make_tab(const double* h) {
     fill_##DD##_##QQ<float, true>(L.prec[1]);                                                     \
     L.eb[0] = Config<DD, QQ, double>::EB;                                                         \
     L.eb[1] = Config<DD, QQ, float>::EB;                                                          \
+    TANGENTS(L);                                                                                  \
     return L;                                                                                     \
   }
 

@@ -620,6 +620,23 @@ feod_status feod_element_vectors(feod_ctx* c, int32_t op, const double* u, const
   return run_element(c, kop, pr, params(c, u, op > 0 ? v : nullptr, c->d_Y0, c->d_Y1, pr));
 }
 
+feod_status feod_element_tangents(feod_ctx* c, const double* u, int64_t first, int64_t count, double* Ke) {
+  TRY(need_bound(c));
+  TRY(check_vec(c, u, "u"));
+  TRY(check_vec(c, Ke, "Ke"));
+  if (first < 0 || count < 0 || first + count > c->lat.E)
+    return fail(c, FEOD_EINVAL, "element range outside the mesh");
+  if (count > INT32_MAX) return fail(c, FEOD_EINVAL, "too many elements in one call");
+  ElemLaunch fn = c->L->tangent[c->curved ? 1 : 0][pow_kind(c->p)];
+  if (!fn) return fail(c, FEOD_EUNSUPPORTED, "element tangents are built for k <= 4 only");
+  if (overlap(u, (size_t)c->lat.N * 8, Ke, (size_t)count * c->Ne * c->Ne * 8))
+    return fail(c, FEOD_EINVAL, "Ke overlaps u");
+  ElemParams P = params(c, u, nullptr, Ke, nullptr, 0);
+  P.e_first = (int32_t)first;
+  P.E = (int32_t)count;
+  return timed(c, "element_tangent_f64", [&] { return fn(P, c->stream); });
+}
+
 feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev) {
   TRY(need_bound(c));
   TRY(check_vec(c, u, "u"));

@@ -23,6 +23,7 @@ struct ElemParams {
   void* out1;             // second E-vector (residual + JVP)
   const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
+  int32_t e_first;        // first element (element-tangent kernel; E is then the count)
   int32_t k, Lx, Ly, Lz;  // order and node-lattice extents (k n + 1 per direction)
   double hinv[3];         // affine meshes: 1/h per direction
   double det;             // affine meshes: element volume h_x h_y h_z
@@ -57,6 +58,7 @@ struct ElemLaunchers {
   struct PerPrec {
     ElemLaunch op[OP_COUNT][2][5];  // [op][curved][PowKind]
   } prec[2];                     // [0] FP64, [1] FP32
+  ElemLaunch tangent[2][5];      // element tangent matrices, FP64: [curved][PowKind] (D1 <= 5)
   int eb[2];
 };
 

@@ -1,0 +1,210 @@
+// Element tangent matrices K_e = d r_e / d u_e = B^T J_D(u_q) B (paper, Eq. 3),
+// with J_D obtained at each quadrature point by forward-mode dual numbers
+// (three directional evaluations of the flux) -- the quadrature-point ("RES")
+// placement of AD the paper argues for, as opposed to differentiating through
+// B at element level.
+//
+// One workgroup per element.  With Chat_q = rho w det Jg^{-1} J_D Jg^{-T}
+// (3x3 per point) and psi_d the reference derivative of a basis function in
+// direction d, K[i][j] = sum_q sum_{d,d'} psi_d(q,i) Chat_dd'(q) psi_d'(q,j).
+// Each psi is a product of 1D factors, so every (d,d') term is contracted by
+// sum factorisation in three stages (x, then y, then z) through LDS:
+// O(nq^3 D1^2 + nq^2 D1^4 + nq D1^6) per term instead of the dense
+// O(nq^3 D1^6).  Supported for D1 <= 5 (the y-stage buffer nq D1^4 must fit).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "element_kernel.hpp"
+
+namespace feod {
+
+template <int D1, int NQ, class T, bool CURVED, int PK>
+__global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
+  constexpr int NT = 256;
+  constexpr int Ne = D1 * D1 * D1, NQ3 = NQ * NQ * NQ, NE2 = Ne * Ne;
+  constexpr int PER = (NE2 + NT - 1) / NT;
+  constexpr int D2 = D1 * D1, D4 = D2 * D2;
+  __shared__ T sU[Ne];
+  __shared__ T sG[3][NQ3];
+  __shared__ T sC[9][NQ3];
+  __shared__ T sT1[NQ * NQ * D2];  // [qz][qy][a][a']
+  __shared__ T sT2[NQ * D4];       // [qz][b][b'][a][a']
+  __shared__ T sX[24];
+  __shared__ T sB[NQ * D1], sD[NQ * D1], sW[NQ], sQ[NQ];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < NQ * D1; i += NT) {
+    sB[i] = tb.B[i];
+    sD[i] = tb.D[i];
+  }
+  for (int i = tid; i < NQ; i += NT) {
+    sW[i] = tb.w[i];
+    sQ[i] = tb.xi[i];
+  }
+  const int e = P.e_first + blockIdx.x;
+  const int ex = e % P.nx, ey = (e / P.nx) % P.ny, ez = e / (P.nx * P.ny);
+
+  // gather M u_e (lattice map; Dirichlet nodes read as 0) and the vertices
+  for (int i = tid; i < Ne; i += NT) {
+    const int a = i % D1, b = (i / D1) % D1, c = i / D2;
+    const int I = P.k * ex + a, J = P.k * ey + b, K = P.k * ez + c;
+    const bool in = I > 0 && I < P.Lx - 1 && J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
+    sU[i] = in ? (T)P.u[I + (int64_t)P.Lx * (J + (int64_t)P.Ly * K)] : T(0);
+  }
+  if (CURVED && tid < 24) {
+    const int vtx = tid / 3, al = tid - vtx * 3;
+    const int gi = (ex + (vtx & 1)) + (P.nx + 1) * ((ey + ((vtx >> 1) & 1)) + (P.ny + 1) * (ez + (vtx >> 2)));
+    sX[tid] = (T)P.verts[(int64_t)gi * 3 + al];
+  }
+  __syncthreads();
+
+  // reference gradients at every point (dense per point; small next to K)
+  for (int q = tid; q < NQ3; q += NT) {
+    const int qx = q % NQ, qy = (q / NQ) % NQ, qz = q / (NQ * NQ);
+    T g0 = 0, g1 = 0, g2 = 0;
+    for (int c = 0; c < D1; ++c)
+      for (int b = 0; b < D1; ++b)
+        for (int a = 0; a < D1; ++a) {
+          const T u = sU[a + D1 * (b + D1 * c)];
+          g0 += sD[qx * D1 + a] * sB[qy * D1 + b] * sB[qz * D1 + c] * u;
+          g1 += sB[qx * D1 + a] * sD[qy * D1 + b] * sB[qz * D1 + c] * u;
+          g2 += sB[qx * D1 + a] * sB[qy * D1 + b] * sD[qz * D1 + c] * u;
+        }
+    sG[0][q] = g0;
+    sG[1][q] = g1;
+    sG[2][q] = g2;
+  }
+  __syncthreads();
+
+  // Chat at every point: J_D by three forward-mode evaluations of the flux
+  const T rho = P.rho != nullptr ? (T)P.rho[e] : T(1);
+  for (int q = tid; q < NQ3; q += NT) {
+    const int qx = q % NQ, qy = (q / NQ) % NQ, qz = q / (NQ * NQ);
+    const T w3 = sW[qx] * sW[qy] * sW[qz];
+    T adj[3][3], det, gu[3];
+    if (CURVED) {
+      const T xi = sQ[qx], et = sQ[qy], ze = sQ[qz];
+      const T mx = T(1) - xi, me = T(1) - et, mz = T(1) - ze;
+      T Jm[3][3];
+      for (int al = 0; al < 3; ++al) {
+        const T* x = sX + al;
+        Jm[al][0] = (me * mz) * (x[3] - x[0]) + (et * mz) * (x[9] - x[6]) + (me * ze) * (x[15] - x[12]) + (et * ze) * (x[21] - x[18]);
+        Jm[al][1] = (mx * mz) * (x[6] - x[0]) + (xi * mz) * (x[9] - x[3]) + (mx * ze) * (x[18] - x[12]) + (xi * ze) * (x[21] - x[15]);
+        Jm[al][2] = (mx * me) * (x[12] - x[0]) + (xi * me) * (x[15] - x[3]) + (mx * et) * (x[18] - x[6]) + (xi * et) * (x[21] - x[9]);
+      }
+      adj[0][0] = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+      adj[0][1] = Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2];
+      adj[0][2] = Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1];
+      adj[1][0] = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+      adj[1][1] = Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0];
+      adj[1][2] = Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2];
+      adj[2][0] = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+      adj[2][1] = Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1];
+      adj[2][2] = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+      det = Jm[0][0] * adj[0][0] + Jm[0][1] * adj[1][0] + Jm[0][2] * adj[2][0];
+      for (int a = 0; a < 3; ++a) gu[a] = (adj[0][a] * sG[0][q] + adj[1][a] * sG[1][q] + adj[2][a] * sG[2][q]) / det;
+    } else {
+      det = (T)P.det;
+      for (int a = 0; a < 3; ++a) gu[a] = sG[a][q] * (T)P.hinv[a];
+    }
+    T Tm[3][3];
+    for (int d = 0; d < 3; ++d) {
+      dual<T> gd[3], Fd[3];
+      for (int a = 0; a < 3; ++a) gd[a] = {gu[a], a == d ? T(1) : T(0)};
+      flux<PK, dual<T>, T>(gd, (T)P.eps2, (T)P.r, Fd);
+      for (int a = 0; a < 3; ++a) Tm[a][d] = Fd[a].d;
+    }
+    const T s = rho * w3;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        T cij;
+        if (CURVED) {
+          T acc = 0;
+          for (int m = 0; m < 3; ++m)
+            for (int n = 0; n < 3; ++n) acc += adj[i][m] * Tm[m][n] * adj[j][n];
+          cij = s * acc / det;
+        } else {
+          cij = s * det * (T)P.hinv[i] * (T)P.hinv[j] * Tm[i][j];
+        }
+        sC[i * 3 + j][q] = cij;
+      }
+  }
+  __syncthreads();
+
+  T acc[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) acc[m] = 0;
+  for (int d = 0; d < 3; ++d) {
+    for (int d2 = 0; d2 < 3; ++d2) {
+      const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
+      const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
+      const T* Fy0 = d == 1 ? sD : sB;
+      const T* Fy1 = d2 == 1 ? sD : sB;
+      const T* Fz0 = d == 2 ? sD : sB;
+      const T* Fz1 = d2 == 2 ? sD : sB;
+      const T* Cdd = sC[d * 3 + d2];
+      // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
+      for (int i = tid; i < NQ * NQ * D2; i += NT) {
+        const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
+        T sacc = 0;
+        for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
+        sT1[i] = sacc;
+      }
+      __syncthreads();
+      // y: T2[qz][b][b'][a][a'] = sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
+      for (int i = tid; i < NQ * D4; i += NT) {
+        const int aa = i % D2, bb = (i / D2) % D2, qz = i / D4, b = bb / D1, b2 = bb % D1;
+        T sacc = 0;
+        for (int qy = 0; qy < NQ; ++qy) sacc += Fy0[qy * D1 + b] * Fy1[qy * D1 + b2] * sT1[(qz * NQ + qy) * D2 + aa];
+        sT2[i] = sacc;
+      }
+      __syncthreads();
+      // z: K[c][c'][b][b'][a][a'] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][b][b'][a][a']
+#pragma unroll
+      for (int m = 0; m < PER; ++m) {
+        const int L = tid + m * NT;
+        if (L < NE2) {
+          const int ab = L % D4, cc = L / D4, c = cc / D1, c2 = cc % D1;
+          T sacc = 0;
+          for (int qz = 0; qz < NQ; ++qz) sacc += Fz0[qz * D1 + c] * Fz1[qz * D1 + c2] * sT2[qz * D4 + ab];
+          acc[m] += sacc;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // K_e row i = a + D1 (b + D1 c), column j = a' + D1 (b' + D1 c'), row-major
+  T* Ke = static_cast<T*>(P.out0) + (int64_t)blockIdx.x * NE2;
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int L = tid + m * NT;
+    if (L < NE2) {
+      const int a2 = L % D1, a = (L / D1) % D1, b2 = (L / D2) % D1, b = (L / (D2 * D1)) % D1;
+      const int c2 = (L / D4) % D1, c = L / (D4 * D1);
+      Ke[(a + D1 * (b + D1 * c)) * Ne + (a2 + D1 * (b2 + D1 * c2))] = acc[m];
+    }
+  }
+}
+
+#define FEOD_INSTANTIATE_TANGENT(DD, QQ)                                                            \
+  template <bool CURVED, int PK>                                                                    \
+  static hipError_t tangent_##DD##_##QQ(const ElemParams& P, hipStream_t s) {                       \
+    if (P.E == 0) return hipSuccess;                                                                \
+    const Tab<DD, QQ, double> tb = make_tab<DD, QQ, double>(P.htab);                                \
+    hipLaunchKernelGGL((tangent_kernel<DD, QQ, double, CURVED, PK>), dim3(P.E), dim3(256), 0, s, P, tb); \
+    return hipGetLastError();                                                                       \
+  }                                                                                                 \
+  template <bool CURVED>                                                                            \
+  static void fill_tangent_##DD##_##QQ(ElemLaunch (&t)[2][5]) {                                     \
+    t[CURVED][POW_ZERO] = &tangent_##DD##_##QQ<CURVED, POW_ZERO>;                                   \
+    t[CURVED][POW_QUARTER] = &tangent_##DD##_##QQ<CURVED, POW_QUARTER>;                             \
+    t[CURVED][POW_HALF] = &tangent_##DD##_##QQ<CURVED, POW_HALF>;                                   \
+    t[CURVED][POW_ONE] = &tangent_##DD##_##QQ<CURVED, POW_ONE>;                                     \
+    t[CURVED][POW_GENERIC] = &tangent_##DD##_##QQ<CURVED, POW_GENERIC>;                             \
+  }                                                                                                 \
+  void fill_tangents_##DD##_##QQ(ElemLaunchers& L) {                                                \
+    fill_tangent_##DD##_##QQ<false>(L.tangent);                                                     \
+    fill_tangent_##DD##_##QQ<true>(L.tangent);                                                      \
+  }
+
+}  // namespace feod

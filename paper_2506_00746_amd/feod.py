@@ -77,6 +77,7 @@ _SIGS = {
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P]),
+    "feod_element_tangents": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
     "feod_element_vectors": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int]),
     "feod_jacobian_diagonal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_newton_solve": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -245,6 +246,19 @@ class Problem:
         vp = None if v is None else _dptr(v, self.n_dofs, "v")
         _check(lib().feod_element_vectors(self._ctx, {"residual": 0, "jvp": 1, "resjvp": 2}[op],
                                           _dptr(u, self.n_dofs, "u"), vp, PREC[prec]), self._ctx)
+
+    def element_tangents(self, u, first=0, count=None, out=None):
+        """K_e (Eq. 3) for elements first..first+count-1: (count, Ne, Ne) FP64."""
+        count = self.n_elems - first if count is None else count
+        ne = (self.k + 1) ** 3
+        if out is None:
+            out = torch.empty((count, ne, ne), dtype=torch.float64, device=self.device)
+        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != count * ne * ne:
+            raise ValueError("out must be a contiguous float64 tensor of count * Ne * Ne entries")
+        self._sync_stream()
+        _check(lib().feod_element_tangents(self._ctx, _dptr(u, self.n_dofs, "u"), first, count,
+                                           out.data_ptr()), self._ctx)
+        return out
 
     def energy(self, u):
         e = torch.empty(1, dtype=torch.float64, device=self.device)

@@ -160,3 +160,35 @@ def test_jacobian_diagonal_matches_assembled_oracle(w):
     assert relerr(d, d_o) <= 1e-12
     dm = host(prob.jacobian_diagonal(dev(inp["u"]), prec="mixed"))
     assert relerr(dm, d_o) <= 1e-5
+
+
+@pytest.mark.parametrize("w", [SMALL[0], SMALL[1], SMALL[2], SMALL[3], SMALL[4], SMALL[5], SMALL[7], SMALL[8]],
+                         ids=["c1", "q2-rho", "q2-curved", "q3-p4", "q3-curved", "q4", "q1-curved", "q2-generic"])
+def test_element_tangents_match_oracle(w):
+    announce("element tangents", w)
+    prob, ora, inp = setup(w)
+    Ke = host(prob.element_tangents(dev(inp["u"])))
+    Ko = ora.element_tangents(inp["u"], np.arange(ora.E))
+    assert relerr(Ke, Ko) <= 1e-12
+    # a sub-range of elements gives the same matrices
+    part = host(prob.element_tangents(dev(inp["u"]), first=1, count=ora.E - 2))
+    assert np.array_equal(part, Ke[1:-1])
+
+
+def test_element_tangents_sampled_on_design_mesh():
+    w = WORKLOADS["c4"]
+    announce("element tangents c4 sampled")
+    prob, ora, inp = setup(w, compute_load=False)
+    rng = np.random.default_rng(0)
+    for first in rng.choice(ora.E - 16, 4, replace=False):
+        Ke = host(prob.element_tangents(dev(inp["u"]), first=int(first), count=16))
+        Ko = ora.element_tangents(inp["u"], np.arange(first, first + 16))
+        assert relerr(Ke, Ko) <= 1e-12
+
+
+def test_element_tangents_unsupported_order():
+    import paper_2506_00746_amd as feod
+    w = SMALL[6]  # Q7
+    prob, _, inp = setup(w, oracle=False)
+    with pytest.raises(feod.FeodError, match="UNSUPPORTED"):
+        prob.element_tangents(dev(inp["u"]))

@@ -134,3 +134,23 @@ def test_sampled_outputs_equal_full():
                           d.residual(inp["u"])[dofs][[1, 2, 3]]) or \
         relerr(d.residual_at(inp["u"], dofs), d.residual(inp["u"])[dofs]) < 1e-14
     assert relerr(d.jvp_at(inp["u"], inp["v"], dofs), d.jvp(inp["u"], inp["v"])[dofs]) < 1e-14
+
+
+def test_element_tangents_assemble_to_jacobian_and_match_fd():
+    d, inp = _disc(2, 2, 2, 2, 3, 3.0, 1e-2, perturb=True, rho=True)
+    u = inp["u"]
+    elems = np.arange(d.E)
+    Ke = d.element_tangents(u, elems)
+    # symmetric element matrices; K_e v_e equals the element Jacobian action
+    assert np.abs(Ke - np.swapaxes(Ke, 1, 2)).max() <= 1e-13 * np.abs(Ke).max()
+    v = inp["v"]
+    ve = d.gather(v, elems)
+    assert relerr(np.einsum("eab,eb->ea", Ke, ve), d.element_jvp(u, v, elems)) < 1e-13
+    # central differences of the element residual in one local direction
+    for e, j in [(0, 13), (0, 26), (5, 4)]:
+        h = 1e-6
+        assert d.mask[d.elem_dofs[e, j]] > 0
+        du = np.zeros(d.N)
+        du[d.elem_dofs[e, j]] = h
+        fd = (d.element_residual(u + du, [e]) - d.element_residual(u - du, [e]))[0] / (2 * h)
+        assert relerr(Ke[e][:, j], fd) < 1e-7
