@@ -129,32 +129,51 @@ def apply_rows(prob, u, v, w, args, only=None):
 
 
 def solve_rows(feod, WORKLOADS, make_inputs, dev):
-    """Newton-CG and adjoint-gradient wall times on the design workload (c4)."""
+    """Newton-CG and adjoint-gradient wall times (synchronised) on the design
+    workload (c4) and the 32^3 Q3 workload (c2): FP64 vs mixed, with and
+    without partial assembly inside CG and Jacobi preconditioning."""
     import torch
     out = {}
-    w = WORKLOADS["c4"]
-    ii = make_inputs(w)
-    pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, rho=ii["rho"], device=dev)
-    b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load, device=dev)
-    u, rep = pb.newton_solve(rtol=1e-10)
-    out["c4_newton_fp64"] = {k: rep[k] for k in ("newton_iters", "cg_iters_total", "res_final", "ref_norm",
-                                                 "seconds")}
-    g64 = None
-    for prec in ("fp64", "mixed"):
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        g, lam, rep = pb.adjoint_gradient(u, b, rtol=1e-10, prec=prec)
-        torch.cuda.synchronize()
-        row = {"ms": (time.perf_counter() - t0) * 1e3, "cg_iters": rep["cg_iters_total"],
-               "refine_iters": rep["refine_iters"], "res_final_rel": rep["res_final"] / rep["ref_norm"]}
-        if g64 is None:
-            g64 = g.clone()
-        else:
-            row["grad_rel_err_vs_fp64"] = float(torch.linalg.norm(g - g64) / torch.linalg.norm(g64))
-        out[f"c4_adjoint_gradient_{prec}"] = row
-    log(f"[bench] solves: {out}")
-    del pb
-    torch.cuda.empty_cache()
+    for name in ("c4", "c2"):
+        w = WORKLOADS[name]
+        ii = make_inputs(w)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, rho=ii["rho"], device=dev)
+        b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load, device=dev)
+        u_ref = None
+        for prec in ("fp64", "mixed"):
+            for pa in (0, 1):
+                for jac in (0, 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    u, rep = pb.newton_solve(rtol=1e-10, prec=prec, partial_assembly=pa, jacobi=jac)
+                    torch.cuda.synchronize()
+                    row = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iters": rep["newton_iters"],
+                           "cg_iters": rep["cg_iters_total"], "res_final_rel": rep["res_final"] / rep["ref_norm"]}
+                    if u_ref is None:
+                        u_ref = u.clone()
+                    else:
+                        row["u_rel_diff_vs_fp64"] = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
+                    out[f"{name}_newton_{prec}_pa{pa}_jacobi{jac}"] = row
+        if name == "c4":
+            g_ref = None
+            for prec in ("fp64", "mixed"):
+                for pa in (0, 1):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    g, lam, rep = pb.adjoint_gradient(u_ref, b, rtol=1e-10, prec=prec, partial_assembly=pa)
+                    torch.cuda.synchronize()
+                    row = {"ms": (time.perf_counter() - t0) * 1e3, "cg_iters": rep["cg_iters_total"],
+                           "refine_iters": rep["refine_iters"],
+                           "res_final_rel": rep["res_final"] / rep["ref_norm"]}
+                    if g_ref is None:
+                        g_ref = g.clone()
+                    else:
+                        row["grad_rel_diff_vs_fp64"] = float(torch.linalg.norm(g - g_ref) / torch.linalg.norm(g_ref))
+                    out[f"c4_adjoint_gradient_{prec}_pa{pa}"] = row
+        del pb
+        torch.cuda.empty_cache()
+    for k, v in out.items():
+        log(f"[bench] solve {k}: {v}")
     return out
 
 
@@ -189,6 +208,33 @@ def tangent_rows(feod, WORKLOADS, make_inputs, dev, args):
                      "GB/s": bytes_ / (ms * 1e-3) / 1e9, "matrix_entries": Ke.numel()}
         log(f"[bench] element tangents {name}: {out[name]}")
         del pb, u, Ke
+        torch.cuda.empty_cache()
+    return out
+
+
+def partial_assembly_rows(feod, WORKLOADS, make_inputs, dev, args):
+    """Fused Jacobian apply vs the partial-assembly one (stored gradients of u)."""
+    import torch
+    out = {}
+    for name in ("c2", "c4", "c5"):
+        w = WORKLOADS[name]
+        ii = make_inputs(w)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=ii["vertices"], rho=ii["rho"],
+                          device=dev)
+        u = torch.as_tensor(ii["u"], device=dev)
+        v = torch.as_tensor(ii["v"], device=dev)
+        jv = torch.empty_like(u)
+        row = {}
+        for prec in ("fp64", "mixed"):
+            t_fused = timed_loop(lambda: pb.jacobian_apply(u, v, out=jv, prec=prec), args.steps, args.warmup)
+            t_setup = timed_loop(lambda: pb.pa_setup(u, prec=prec), 5, 1)
+            t_pa = timed_loop(lambda: pb.jacobian_apply_pa(v, out=jv, prec=prec), args.steps, args.warmup)
+            row[prec] = {"fused_us": t_fused * 1e3, "pa_us": t_pa * 1e3, "pa_setup_us": t_setup * 1e3,
+                         "pa_speedup": t_fused / t_pa,
+                         "stored_MB": 3 * w.nq ** 3 * w.n_elems * (8 if prec == "fp64" else 4) / 1e6}
+        out[name] = row
+        log(f"[bench] partial assembly {name}: {row}")
+        del pb, u, v, jv
         torch.cuda.empty_cache()
     return out
 
@@ -285,6 +331,7 @@ def main():
             torch.cuda.empty_cache()
         rows["solves"] = solve_rows(feod, WORKLOADS, make_inputs, dev)
         rows["element_tangents"] = tangent_rows(feod, WORKLOADS, make_inputs, dev, args)
+        rows["partial_assembly"] = partial_assembly_rows(feod, WORKLOADS, make_inputs, dev, args)
 
     cpu = None
     if not args.no_cpu_baseline:

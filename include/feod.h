@@ -97,6 +97,8 @@ typedef struct {
   feod_prec prec;
   int32_t init_poisson;
   int32_t jacobi;    /* 1: precondition CG with diag J(u) (Jacobi), 0: none */
+  int32_t partial_assembly; /* 1: CG applies J(u) from the stored gradients of u
+                               (feod_pa_setup once per linearisation), 0: fused */
 } feod_solver_opts;
 
 typedef struct {
@@ -118,7 +120,9 @@ typedef struct {
 } feod_kernel_stat;
 
 /* Fill opts with defaults: rtol 1e-10, cg_rtol_floor 1e-12, max_newton 50,
- * max_cg 20000, max_ls 30, check_every 10, FP64, init_poisson 1, jacobi 0. */
+ * max_cg 20000, max_ls 30, check_every 10, FP64, init_poisson 1, jacobi 1,
+ * partial_assembly 1 (measured fastest on the 48^3 Q2 and 32^3 Q3 workloads:
+ * Jacobi halves the CG iterations, partial assembly saves 7-10%). */
 void feod_default_opts(feod_solver_opts* opts);
 
 /* Build the mesh, element-to-DOF map G, transposed map for G^T, 1D tables and
@@ -177,6 +181,16 @@ feod_status feod_element_vectors(feod_ctx* ctx, int32_t op, const double* u, con
 feod_status feod_element_tangents(feod_ctx* ctx, const double* u, int64_t first, int64_t count,
                                   double* Ke);
 
+/* Partial assembly (the pointwise data of Fig. 1's caption): store the
+ * reference gradients of M u at every quadrature point (3 per point, in the
+ * precision of prec) in the workspace, so that feod_jacobian_apply_pa can
+ * apply J(u) without recomputing the gradient of u. */
+feod_status feod_pa_setup(feod_ctx* ctx, const double* u, feod_prec prec);
+
+/* jv = M J(u) M v at the u of the last feod_pa_setup with the same prec
+ * (FEOD_ESTATE otherwise).  v, jv: device, length N. */
+feod_status feod_jacobian_apply_pa(feod_ctx* ctx, const double* v, double* jv, feod_prec prec);
+
 /* Energy E(u) = sum_e rho_e int_e (1/p)(eps^2+|grad Mu|^2)^(p/2) - b^T M u,
  * whose gradient is R (line-search merit function).  e_dev: device, 1 double. */
 feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev);
@@ -223,7 +237,8 @@ feod_status feod_profile_read(feod_ctx* ctx, feod_kernel_stat* stats, int32_t ma
 
 /* Algorithmic cost of one launch of the fused element kernel for an
  * operation (0 residual, 1 Jacobian apply, 2 residual+Jacobian, 3 energy,
- * 4 gradient, 5 diagonal) at precision prec: bytes moved to/from HBM by the
+ * 4 gradient, 6 partial-assembly set-up, 7 partial-assembly Jacobian apply;
+ * 5 (diagonal) is not modelled) at precision prec: bytes moved to/from HBM by the
  * design (unique reads of inputs and maps, E-vector writes) and floating
  * point operations (FMA = 2).  Host only. */
 feod_status feod_kernel_cost(const feod_ctx* ctx, int32_t op, feod_prec prec,

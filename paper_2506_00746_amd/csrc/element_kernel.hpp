@@ -185,12 +185,13 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   constexpr int EB = C::EB;
   constexpr int Ne = D1 * D1 * D1;
   constexpr int NQ2 = NQ * NQ;
-  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD) ? 2 : 1;  // input fields
+  constexpr bool PA = OP == OP_JVP_PA, QSTORE = OP == OP_QSTORE;
+  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD || PA) ? 2 : 1;  // register fields
   constexpr int O = (OP == OP_RESJVP) ? 2 : 1;                                    // output fields
   constexpr bool REDUCE = (OP == OP_ENERGY || OP == OP_GRAD);
-  constexpr bool SEQ = C::SEQ && F == 2;
+  constexpr bool SEQ = C::SEQ && F == 2 && !PA;
   static_assert(!SEQ || EB * NQ2 <= NT, "sequential fields need one phase-C line per thread");
-  constexpr int FX = SEQ ? 1 : F;  // fields resident in the x-pass buffer at once
+  constexpr int FX = (SEQ || PA) ? 1 : F;  // fields resident in the x-pass buffer at once
   constexpr bool DIAG = OP == OP_DIAG;
   // z-back fields: 3 per output (x, y, z flux components); the diagonal has 6
   // (the symmetric tensor terms); y-back blocks: 2 per output, 3 for the diagonal
@@ -237,7 +238,10 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   __syncthreads();  // sE, tables and vertices visible to every thread
 
   // ---- A: gather + x-pass ---------------------------------------------------
-  if constexpr (F == 2 && !SEQ) {
+  if constexpr (PA) {
+    const double* const src[1] = {P.v};
+    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+  } else if constexpr (F == 2 && !SEQ) {
     const double* const src[2] = {P.u, P.v};
     phase_a<D1, NQ, EB, NT, L::X, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
   } else {
@@ -277,7 +281,25 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       By[b] = sB[qy * L::XQ + b];
       Dy[b] = sD[qy * L::XQ + b];
     }
-    if constexpr (SEQ) {
+    if constexpr (QSTORE) {
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[0]);
+      if (el < n_valid) {
+        T* qd = static_cast<T*>(P.qdata) + (int64_t)(e0 + el) * 3 * NQ * NQ2 + qxy;
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+#pragma unroll
+          for (int qz = 0; qz < NQ; ++qz) qd[(d * NQ + qz) * NQ2] = g[0][d][qz];
+      }
+      continue;
+    } else if constexpr (PA) {
+      // v from the x-pass buffer; u's reference gradients from the stored data
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[1]);
+      const T* qd = static_cast<const T*>(P.qdata) + (int64_t)(e0 + (el < n_valid ? el : 0)) * 3 * NQ * NQ2 + qxy;
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int qz = 0; qz < NQ; ++qz) g[0][d][qz] = qd[(d * NQ + qz) * NQ2];
+    } else if constexpr (SEQ) {
       column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[1]);
     } else {
 #pragma unroll
@@ -389,7 +411,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
         cd[5][qz] = Ch[1][2] + Ch[2][1];
       } else if constexpr (OP == OP_RESIDUAL) {
         flux<PK, T, T>(gu, eps2, r, Fo[0]);
-      } else if constexpr (OP == OP_JVP || OP == OP_RESJVP) {
+      } else if constexpr (OP == OP_JVP || OP == OP_RESJVP || PA) {
         dual<T> gd[3], Fd[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) gd[a] = {gu[a], gv[a]};
@@ -468,6 +490,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   }
   __syncthreads();
 
+  if constexpr (QSTORE) return;
   if constexpr (REDUCE) {
     const int lane = tid & 63, wv = tid >> 6;
     double* outd = static_cast<double*>(P.out0);
@@ -641,6 +664,8 @@ inline void no_tangents(ElemLaunchers&) {}
     t.op[OP_ENERGY][CURVED][PK] = &launch_##DD##_##QQ<T, OP_ENERGY, CURVED, PK>;                  \
     t.op[OP_GRAD][CURVED][PK] = &launch_##DD##_##QQ<T, OP_GRAD, CURVED, PK>;                      \
     t.op[OP_DIAG][CURVED][PK] = &launch_##DD##_##QQ<T, OP_DIAG, CURVED, PK>;                      \
+    t.op[OP_QSTORE][CURVED][PK] = &launch_##DD##_##QQ<T, OP_QSTORE, CURVED, PK>;                  \
+    t.op[OP_JVP_PA][CURVED][PK] = &launch_##DD##_##QQ<T, OP_JVP_PA, CURVED, PK>;                  \
   }                                                                                               \
   template <class T, bool CURVED>                                                                 \
   static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                       \

@@ -54,7 +54,8 @@ struct feod_ctx {
   float* d_tab32 = nullptr;
   int32_t *d_emap = nullptr, *d_toff = nullptr, *d_tidx = nullptr;
   double *d_bm = nullptr, *d_rho = nullptr, *d_verts = nullptr, *d_elem = nullptr;
-  void *d_Y0 = nullptr, *d_Y1 = nullptr;
+  void *d_Y0 = nullptr, *d_Y1 = nullptr, *d_qdata = nullptr;
+  int pa_prec = -1;  // precision of the stored partial-assembly data, -1: none
   double* d_vec[kNumVec] = {};
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_sc = nullptr;
   // profiling
@@ -100,7 +101,7 @@ int pow_kind(double p) {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t tab64, tab32, emap, toff, tidx, bm, rho, verts, elem, Y0, Y1, vec, part0, part1, sc, total;
+  size_t tab64, tab32, emap, toff, tidx, bm, rho, verts, elem, Y0, Y1, qdata, vec, part0, part1, sc, total;
 };
 
 Layout layout(const feod_ctx* c) {
@@ -124,6 +125,7 @@ Layout layout(const feod_ctx* c) {
   l.elem = take(E * 8);
   l.Y0 = take(Ene * 8);
   l.Y1 = take(Ene * 8);
+  l.qdata = take(E * 3 * (size_t)c->NQ3 * 8);  // partial assembly: stored reference gradients
   l.vec = take(kNumVec * align_up(N * 8));
   l.part0 = take(kRedBlocks * 8);
   l.part1 = take(kRedBlocks * 8);
@@ -215,6 +217,7 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
   P.tab = prec ? (const void*)c->d_tab32 : (const void*)c->d_tab64;
   P.out0 = out0;
   P.out1 = out1;
+  P.qdata = c->d_qdata;
   P.E = (int32_t)c->lat.E;
   P.nx = c->nx;
   P.ny = c->ny;
@@ -236,9 +239,11 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
 
 const char* op_name(int op, int prec) {
   static const char* n64[] = {"element_residual_f64", "element_jvp_f64", "element_resjvp_f64",
-                              "element_energy_f64", "element_grad_f64", "element_diag_f64"};
+                              "element_energy_f64", "element_grad_f64", "element_diag_f64",
+                              "element_qstore_f64", "element_jvp_pa_f64"};
   static const char* n32[] = {"element_residual_f32", "element_jvp_f32", "element_resjvp_f32",
-                              "element_energy_f32", "element_grad_f32", "element_diag_f32"};
+                              "element_energy_f32", "element_grad_f32", "element_diag_f32",
+                              "element_qstore_f32", "element_jvp_pa_f32"};
   return prec ? n32[op] : n64[op];
 }
 
@@ -322,8 +327,11 @@ struct CgResult {
   feod_status status = FEOD_OK;
 };
 
+// J applies use the fused kernel at u, or (pa) the stored partial-assembly data
+// of u in precision prec (set up by the caller).
 feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double rtol, int max_it,
-               int check_every, int prec, const double* dinv, CgResult* out, double p_override = 0.0) {
+               int check_every, int prec, const double* dinv, CgResult* out, double p_override = 0.0,
+               bool pa = false) {
   const int64_t N = c->lat.N;
   double* r = c->d_vec[V_CR];
   double* p = c->d_vec[V_CP];
@@ -358,7 +366,12 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
   TRY(timed(c, "axpby", [&] { return launch_axpby(p, 1.0, z, 0.0, nullptr, N, c->stream); }));
   const double tol = rtol * out->bnorm;
   for (int it = 0; it < max_it; ++it) {
-    TRY(apply_jvp(c, u, p, q, nullptr, prec, p_override));
+    if (pa) {
+      TRY(run_element(c, OP_JVP_PA, prec, params(c, nullptr, p, c->d_Y0, nullptr, prec)));
+      TRY(timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, q, nullptr); }));
+    } else {
+      TRY(apply_jvp(c, u, p, q, nullptr, prec, p_override));
+    }
     TRY(dot(c, p, q, N, c->d_sc + S_PQ));
     TRY(timed(c, "cg_update", [&] {
       return launch_cg_update(x, r, z, p, q, dinv, c->d_sc, cur, S_PQ, N, c->d_part0, c->d_part1, c->stream);
@@ -426,7 +439,8 @@ void feod_default_opts(feod_solver_opts* o) {
   o->check_every = 10;
   o->prec = FEOD_FP64;
   o->init_poisson = 1;
-  o->jacobi = 0;
+  o->jacobi = 1;
+  o->partial_assembly = 1;
 }
 
 feod_status feod_setup_mesh(const feod_mesh_desc* d, feod_ctx** out) {
@@ -529,6 +543,8 @@ feod_status feod_bind_workspace(feod_ctx* c, void* dev, size_t bytes) {
   c->d_elem = (double*)(w + l.elem);
   c->d_Y0 = w + l.Y0;
   c->d_Y1 = w + l.Y1;
+  c->d_qdata = w + l.qdata;
+  c->pa_prec = -1;
   const size_t vstride = align_up((size_t)c->lat.N * 8);
   for (int i = 0; i < kNumVec; ++i) c->d_vec[i] = (double*)(w + l.vec + i * vstride);
   c->d_part0 = (double*)(w + l.part0);
@@ -637,6 +653,29 @@ feod_status feod_element_tangents(feod_ctx* c, const double* u, int64_t first, i
   return timed(c, "element_tangent_f64", [&] { return fn(P, c->stream); });
 }
 
+feod_status feod_pa_setup(feod_ctx* c, const double* u, feod_prec prec) {
+  TRY(need_bound(c));
+  TRY(check_prec(c, prec));
+  TRY(check_vec(c, u, "u"));
+  const int pr = prec == FEOD_MIXED;
+  TRY(run_element(c, OP_QSTORE, pr, params(c, u, nullptr, nullptr, nullptr, pr)));
+  c->pa_prec = pr;
+  return FEOD_OK;
+}
+
+feod_status feod_jacobian_apply_pa(feod_ctx* c, const double* v, double* jv, feod_prec prec) {
+  TRY(need_bound(c));
+  TRY(check_prec(c, prec));
+  TRY(check_vec(c, v, "v"));
+  TRY(check_vec(c, jv, "jv"));
+  const int pr = prec == FEOD_MIXED;
+  if (c->pa_prec != pr) return fail(c, FEOD_ESTATE, "feod_pa_setup has not been called for this precision");
+  const size_t nb = (size_t)c->lat.N * 8;
+  if (overlap(v, nb, jv, nb)) return fail(c, FEOD_EINVAL, "jv overlaps v");
+  TRY(run_element(c, OP_JVP_PA, pr, params(c, nullptr, v, c->d_Y0, nullptr, pr)));
+  return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, pr == 1, nullptr, jv, nullptr); });
+}
+
 feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev) {
   TRY(need_bound(c));
   TRY(check_vec(c, u, "u"));
@@ -740,7 +779,13 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
       if (feod_status s = jacobi(c, u, c->d_vec[V_DINV], ut); s != FEOD_OK) return finish(s);
       dinv = c->d_vec[V_DINV];
     }
-    if (feod_status s = cg(c, u, rhs, du, eta, o.max_cg, o.check_every, prec, dinv, &cr); s != FEOD_OK)
+    if (o.partial_assembly) {
+      if (feod_status s = run_element(c, OP_QSTORE, prec, params(c, u, nullptr, nullptr, nullptr, prec)); s != FEOD_OK)
+        return finish(s);
+      c->pa_prec = prec;
+    }
+    if (feod_status s = cg(c, u, rhs, du, eta, o.max_cg, o.check_every, prec, dinv, &cr, 0.0, o.partial_assembly);
+        s != FEOD_OK)
       return finish(s);
     rep.cg_iters_total += cr.iters;
     // Armijo backtracking on the energy
@@ -802,8 +847,15 @@ feod_status feod_adjoint_gradient(feod_ctx* c, const double* u, const double* g_
     if (feod_status s = jacobi(c, u, c->d_vec[V_DINV], c->d_vec[V_AUX2]); s != FEOD_OK) return finish(s);
     dinv = c->d_vec[V_DINV];
   }
+  if (o.partial_assembly) {
+    const int pr = o.prec == FEOD_MIXED;
+    if (feod_status s = run_element(c, OP_QSTORE, pr, params(c, u, nullptr, nullptr, nullptr, pr)); s != FEOD_OK)
+      return finish(s);
+    c->pa_prec = pr;
+  }
   if (o.prec == FEOD_FP64) {
-    if (feod_status s = cg(c, u, rhs, lam, o.rtol, o.max_cg, o.check_every, 0, dinv, &cr); s != FEOD_OK)
+    if (feod_status s = cg(c, u, rhs, lam, o.rtol, o.max_cg, o.check_every, 0, dinv, &cr, 0.0, o.partial_assembly);
+        s != FEOD_OK)
       return finish(s);
     rep.cg_iters_total = cr.iters;
     rep.ref_norm = cr.bnorm;
@@ -835,7 +887,8 @@ feod_status feod_adjoint_gradient(feod_ctx* c, const double* u, const double* g_
       if (rn <= o.rtol * rep.ref_norm) break;
       if (k >= 50) return finish(fail(c, FEOD_ENOCONV, "iterative refinement did not converge"));
       const double inner = std::max(1e-5, std::min(1e-3, o.rtol * rep.ref_norm / rn));
-      if (feod_status s = cg(c, u, res, d, inner, o.max_cg, o.check_every, 1, dinv, &cr); s != FEOD_OK)
+      if (feod_status s = cg(c, u, res, d, inner, o.max_cg, o.check_every, 1, dinv, &cr, 0.0, o.partial_assembly);
+          s != FEOD_OK)
         return finish(s);
       rep.cg_iters_total += cr.iters;
       if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(lam, 1.0, lam, 1.0, d, N, c->stream); });
@@ -895,25 +948,27 @@ static double pointwise_flops(int op, int pk, bool curved) {
     case OP_RESJVP: f = 44 + apow_d[pk]; break;    // + value pull-back
     case OP_ENERGY: f = 16 + apow_s[pk]; break;    // a, W = a a^r / p, weight
     case OP_GRAD: f = 22 + apow_s[pk]; break;      // a^r g_u . g_lambda, weight
+    case OP_JVP_PA: f = 38 + apow_d[pk]; break;    // as the Jacobian action
     default: f = 0;
   }
   if (curved) {  // Jacobian, adjugate, determinant, transforms (per-line set-up amortised)
-    const double geo[OP_COUNT] = {78, 93, 105, 66, 81, 0};
+    const double geo[OP_COUNT] = {78, 93, 105, 66, 81, 0, 0, 93};
     f += geo[op];
   }
   return f;
 }
 
 feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, double* bytes, double* flops) {
-  if (!c || !bytes || !flops || op < 0 || op >= OP_DIAG) return fail(nullptr, FEOD_EINVAL, "invalid argument");
+  if (!c || !bytes || !flops || op < 0 || op >= OP_COUNT || op == OP_DIAG)
+    return fail(nullptr, FEOD_EINVAL, "invalid argument");
   const double E = (double)c->lat.E, N = (double)c->lat.N, Ne = c->Ne, nq = c->nq, D1 = c->D1;
   const double NQ3 = (double)c->NQ3;
   const double ts = prec == FEOD_MIXED ? 4.0 : 8.0;
   // one sum-factorised gradient pass (B or B^T) per field, FMA = 2
   const double S = 4 * nq * D1 * D1 * D1 + 6 * nq * nq * D1 * D1 + 6 * nq * nq * nq * D1;
-  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0};
-  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1};
-  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1};
+  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0, 1, 2};
+  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1, 1, 1};
+  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1, 0, 1};
   *flops = E * (passes[op] * S + NQ3 * pointwise_flops(op, pow_kind(c->p), c->curved));
   double b = fields[op] * 8.0 * N;  // unique L-vector reads
   if (c->explicit_maps) b += 4.0 * E * Ne;  // stored element-to-DOF map
@@ -921,6 +976,7 @@ feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, doub
   if (c->curved) b += 24.0 * (c->nx + 1.0) * (c->ny + 1.0) * (c->nz + 1.0);
   b += outs[op] * ts * E * Ne;
   if (op == OP_ENERGY || op == OP_GRAD) b += 8.0 * E;
+  if (op == OP_QSTORE || op == OP_JVP_PA) b += 3.0 * NQ3 * E * ts;  // stored gradients
   *bytes = b;
   return FEOD_OK;
 }

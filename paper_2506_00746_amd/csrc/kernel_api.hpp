@@ -8,7 +8,17 @@ namespace feod {
 // Exponent r = (p-2)/2 of the flux coefficient a^r, specialised by sqrt chains.
 enum PowKind : int { POW_ZERO = 0, POW_QUARTER = 1, POW_HALF = 2, POW_ONE = 3, POW_GENERIC = 4 };
 
-enum : int { OP_RESIDUAL = 0, OP_JVP = 1, OP_RESJVP = 2, OP_ENERGY = 3, OP_GRAD = 4, OP_DIAG = 5, OP_COUNT = 6 };
+enum : int {
+  OP_RESIDUAL = 0,  // E-vector of the residual
+  OP_JVP = 1,       // E-vector of the Jacobian action
+  OP_RESJVP = 2,    // both
+  OP_ENERGY = 3,    // per-element energy
+  OP_GRAD = 4,      // per-element dR/drho weighted by lambda
+  OP_DIAG = 5,      // E-vector of diag(J)
+  OP_QSTORE = 6,    // partial assembly: reference gradients of M u at every point -> qdata
+  OP_JVP_PA = 7,    // Jacobian action with the stored gradients (v gathered only)
+  OP_COUNT = 8
+};
 
 // Arguments of the fused element kernel (passed by value).
 struct ElemParams {
@@ -21,6 +31,7 @@ struct ElemParams {
   const void* tab;        // 1D tables in the kernel precision: B, D (nq x D1), w, xi (nq)
   void* out0;             // E-vector (kernel precision) or E doubles (energy, gradient)
   void* out1;             // second E-vector (residual + JVP)
+  void* qdata;            // partial assembly: [e][d][qz][qy][qx] reference gradients (kernel precision)
   const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
   int32_t e_first;        // first element (element-tangent kernel; E is then the count)

@@ -30,6 +30,7 @@ class DesignSolve(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad_u: torch.Tensor):
         (u,) = ctx.saved_tensors
-        opts = {k: v for k, v in ctx.opts.items() if k in ("rtol", "max_cg", "check_every", "prec")}
+        opts = {k: v for k, v in ctx.opts.items()
+                if k in ("rtol", "max_cg", "check_every", "prec", "jacobi", "partial_assembly")}
         grad_rho, _, _ = ctx.problem.adjoint_gradient(u, grad_u.contiguous().to(torch.float64), **opts)
         return grad_rho, None, None

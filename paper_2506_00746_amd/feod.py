@@ -22,7 +22,7 @@ FEOD_OK, FEOD_EINVAL, FEOD_EUNSUPPORTED, FEOD_EHIP, FEOD_ENOCONV, FEOD_ENONFINIT
 STATUS_NAMES = {0: "FEOD_OK", 1: "FEOD_EINVAL", 2: "FEOD_EUNSUPPORTED", 3: "FEOD_EHIP",
                 4: "FEOD_ENOCONV", 5: "FEOD_ENONFINITE", 6: "FEOD_EBREAKDOWN", 7: "FEOD_ESTATE"}
 PREC = {"fp64": 0, "mixed": 1}
-OPS = {"residual": 0, "jvp": 1, "resjvp": 2, "energy": 3, "grad": 4, "diag": 5}
+OPS = {"residual": 0, "jvp": 1, "resjvp": 2, "energy": 3, "grad": 4, "diag": 5, "pa_setup": 6, "jvp_pa": 7}
 
 
 class FeodError(RuntimeError):
@@ -44,7 +44,7 @@ class SolverOpts(ctypes.Structure):
                 ("max_newton", ctypes.c_int32), ("max_cg", ctypes.c_int32),
                 ("max_ls", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("prec", ctypes.c_int32), ("init_poisson", ctypes.c_int32),
-                ("jacobi", ctypes.c_int32)]
+                ("jacobi", ctypes.c_int32), ("partial_assembly", ctypes.c_int32)]
 
 
 class SolverReport(ctypes.Structure):
@@ -77,6 +77,8 @@ _SIGS = {
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P]),
+    "feod_pa_setup": (ctypes.c_int, [_P, _P, ctypes.c_int]),
+    "feod_jacobian_apply_pa": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_element_tangents": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
     "feod_element_vectors": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int]),
     "feod_jacobian_diagonal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
@@ -258,6 +260,19 @@ class Problem:
         self._sync_stream()
         _check(lib().feod_element_tangents(self._ctx, _dptr(u, self.n_dofs, "u"), first, count,
                                            out.data_ptr()), self._ctx)
+        return out
+
+    def pa_setup(self, u, prec="fp64"):
+        """Partial assembly: store the reference gradients of M u at all points."""
+        self._sync_stream()
+        _check(lib().feod_pa_setup(self._ctx, _dptr(u, self.n_dofs, "u"), PREC[prec]), self._ctx)
+
+    def jacobian_apply_pa(self, v, out=None, prec="fp64"):
+        """J(u) v at the u of the last pa_setup (same precision)."""
+        out = self._vec(out)
+        self._sync_stream()
+        _check(lib().feod_jacobian_apply_pa(self._ctx, _dptr(v, self.n_dofs, "v"), out.data_ptr(), PREC[prec]),
+               self._ctx)
         return out
 
     def energy(self, u):

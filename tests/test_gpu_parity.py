@@ -192,3 +192,21 @@ def test_element_tangents_unsupported_order():
     prob, _, inp = setup(w, oracle=False)
     with pytest.raises(feod.FeodError, match="UNSUPPORTED"):
         prob.element_tangents(dev(inp["u"]))
+
+
+@pytest.mark.parametrize("w", [SMALL[0], SMALL[2], SMALL[4], SMALL[6]], ids=["c1", "q2-curved", "q3-curved", "q7-curved"])
+def test_partial_assembly_jvp_equals_fused(w):
+    import paper_2506_00746_amd as feod
+    announce("partial assembly", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    with pytest.raises(feod.FeodError, match="ESTATE"):
+        prob.jacobian_apply_pa(v)
+    for prec in ("fp64", "mixed"):
+        prob.pa_setup(u, prec=prec)
+        a = host(prob.jacobian_apply_pa(v, prec=prec))
+        b = host(prob.jacobian_apply(u, v, prec=prec))
+        assert np.array_equal(a, b), prec
+    assert relerr(host(prob.jacobian_apply_pa(v, prec="mixed")), ora.jvp(inp["u"], inp["v"])) < 1e-5
+    prob.pa_setup(u)
+    assert relerr(host(prob.jacobian_apply_pa(v)), ora.jvp(inp["u"], inp["v"])) <= 1e-12

@@ -98,3 +98,16 @@ def test_jacobi_preconditioned_newton_and_adjoint(prec):
     g1, _, r1 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec)
     g2, _, r2 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec, jacobi=1)
     assert relerr(host(g2), host(g1)) <= 1e-9
+
+
+def test_partial_assembly_solves_match_fused():
+    w = Workload("pa", 5, 4, 3, 3, 5, 3.0, 1e-2, 34, perturb=True, rho=True)
+    announce("partial assembly solves", w)
+    prob, ora, _ = setup(w)
+    u0, r0 = prob.newton_solve(rtol=1e-12, partial_assembly=0)
+    u1, r1 = prob.newton_solve(rtol=1e-12, partial_assembly=1)
+    assert relerr(host(u1), host(u0)) <= 1e-10
+    b = dev(ora.b)
+    g0, _, _ = prob.adjoint_gradient(u1, b, rtol=1e-12, partial_assembly=0)
+    g1, _, _ = prob.adjoint_gradient(u1, b, rtol=1e-12, partial_assembly=1)
+    assert relerr(host(g1), host(g0)) <= 1e-10
