@@ -84,8 +84,7 @@ typedef struct {
  * The line search is Armijo backtracking on the energy (c = 1e-4, halving,
  * at most max_ls halvings).  check_every: CG reads its residual norm back to
  * the host every this many iterations.  prec: FEOD_MIXED runs the Jacobian
- * applies inside CG in FP32 (residuals, CG vectors, dots and the refinement
- * correction stay FP64).  init_poisson: start Newton from the p = 2 solution
+ * applies inside CG in FP32 (residuals, CG vectors and dots stay FP64).  init_poisson: start Newton from the p = 2 solution
  * instead of the caller's u. */
 typedef struct {
   double rtol;
@@ -104,7 +103,7 @@ typedef struct {
 typedef struct {
   int32_t newton_iters;
   int32_t cg_iters_total;
-  int32_t refine_iters;
+  int32_t refine_iters; /* adjoint, FEOD_MIXED: FP64 true-residual updates */
   int32_t ls_halvings_total;
   double res0;       /* initial residual norm                     */
   double res_final;  /* final residual norm                       */
@@ -213,7 +212,10 @@ feod_status feod_newton_solve(feod_ctx* ctx, double* u, const feod_solver_opts* 
  *             = -sum_q w detJ (eps^2+|grad u|^2)^((p-2)/2) grad u . grad lambda
  * by one per-element kernel (no G^T).  u, g_u, lambda_or_null: device,
  * length N; grad_rho: device, nx*ny*nz.  With FEOD_MIXED the CG runs FP32
- * Jacobian applies inside an FP64 iterative-refinement loop.  Synchronises. */
+ * Jacobian applies and replaces its recursive residual by the FP64 true
+ * residual M g_u - J lambda (reliable updates) whenever the former has dropped
+ * 10x since the last replacement; it stops on the true residual.  The gradient
+ * kernel runs in FP64.  Synchronises. */
 feod_status feod_adjoint_gradient(feod_ctx* ctx, const double* u, const double* g_u,
                                   double* lambda_or_null, double* grad_rho,
                                   const feod_solver_opts* opts,

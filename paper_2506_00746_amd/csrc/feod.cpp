@@ -21,7 +21,9 @@ namespace {
 constexpr int kNumVec = 10;   // solver temporaries of length N
 constexpr int kScalars = 64;  // device scalar slots
 enum Vec { V_R = 0, V_DU, V_CR, V_CP, V_CQ, V_CZ, V_DINV, V_UT, V_AUX, V_AUX2 };
-enum Scal { S_RZ0 = 0, S_RZ1 = 1, S_PQ = 2, S_RR = 3, S_A = 4, S_B = 5, S_E = 6, S_T = 7 };
+enum Scal { S_RZ = 0, S_PQ = 2, S_RR = 3, S_A = 4, S_B = 5, S_E = 6, S_T = 7 };
+// CG partial-sum slots, kCgBlocks doubles each: p.q, r.z (two, alternating), r.r
+enum CgPart { C_PQ = 0, C_RZ0, C_RZ1, C_RR, kCgParts };
 
 thread_local std::string g_setup_error;
 
@@ -57,7 +59,8 @@ struct feod_ctx {
   void *d_Y0 = nullptr, *d_Y1 = nullptr, *d_qdata = nullptr;
   int pa_prec = -1;  // precision of the stored partial-assembly data, -1: none
   double* d_vec[kNumVec] = {};
-  double *d_part0 = nullptr, *d_part1 = nullptr, *d_sc = nullptr;
+  double *d_part0 = nullptr, *d_part1 = nullptr, *d_cgpart = nullptr, *d_sc = nullptr;
+  double* cg_part(int slot) const { return d_cgpart + (size_t)slot * kCgBlocks; }
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;
@@ -101,7 +104,7 @@ int pow_kind(double p) {
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t tab64, tab32, emap, toff, tidx, bm, rho, verts, elem, Y0, Y1, qdata, vec, part0, part1, sc, total;
+  size_t tab64, tab32, emap, toff, tidx, bm, rho, verts, elem, Y0, Y1, qdata, vec, part0, part1, cgpart, sc, total;
 };
 
 Layout layout(const feod_ctx* c) {
@@ -129,6 +132,7 @@ Layout layout(const feod_ctx* c) {
   l.vec = take(kNumVec * align_up(N * 8));
   l.part0 = take(kRedBlocks * 8);
   l.part1 = take(kRedBlocks * 8);
+  l.cgpart = take(kCgParts * kCgBlocks * 8);
   l.sc = take(kScalars * 8);
   l.total = off;
   return l;
@@ -322,16 +326,40 @@ feod_status host_energy(feod_ctx* c, const double* u, double* val) {
 
 // ---- CG on J(u) x = b (J symmetric, SPD on interior DOFs) ------------------
 struct CgResult {
-  int iters = 0;
+  int iters = 0, updates = 0;  // updates: reliable (true-residual) updates
   double res = 0, bnorm = 0;
   feod_status status = FEOD_OK;
 };
 
-// J applies use the fused kernel at u, or (pa) the stored partial-assembly data
-// of u in precision prec (set up by the caller).
+// G^T of the E-vector Y0 into q, with the partial sums of p.q (CG slot C_PQ)
+feod_status gather_t_dot(feod_ctx* c, bool fp32, const double* p, double* q) {
+  return timed(c, "gather_transpose_dot", [&] {
+    if (c->explicit_maps)
+      return launch_gather_t_dot(nullptr, c->d_toff, c->d_tidx, c->d_Y0, fp32, p, q, c->lat.N,
+                                 c->cg_part(C_PQ), c->stream);
+    LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz};
+    return launch_gather_t_dot(&d, nullptr, nullptr, c->d_Y0, fp32, p, q, c->lat.N, c->cg_part(C_PQ), c->stream);
+  });
+}
+
+// Preconditioned CG (Jacobi when dinv != null).  One iteration is four
+// launches: the element kernel on p, G^T fused with the p.q partial sums, the
+// step (alpha, x, r, z and the r.z / r.r partials) and the new direction
+// (beta, p).  Inner products stay on the device as fixed-order partial sums;
+// the host reads them every check_every iterations.  J applies use the fused
+// kernel at u, or (pa) the stored partial-assembly data of u in precision prec
+// (set up by the caller).
+//
+// reliable (with prec = FP32): the recursive residual of a CG whose Jacobian
+// applies are FP32 drifts from the true one.  Whenever it has dropped by
+// kReliableDrop since the last true residual (or below the tolerance), r is
+// replaced by the FP64 true residual b - J64 x (x and p kept), and convergence
+// is decided on that true residual only.
+constexpr double kReliableDrop = 0.1;
+
 feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double rtol, int max_it,
                int check_every, int prec, const double* dinv, CgResult* out, double p_override = 0.0,
-               bool pa = false) {
+               bool pa = false, bool reliable = false) {
   const int64_t N = c->lat.N;
   double* r = c->d_vec[V_CR];
   double* p = c->d_vec[V_CP];
@@ -345,62 +373,65 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
     out->status = FEOD_ENONFINITE;
     return fail(c, FEOD_ENONFINITE, "non-finite right-hand side in CG");
   }
-  TRY(timed(c, "fill", [&] { return launch_fill(x, 0.0, N, c->stream); }));
   if (bn2 == 0.0) {
     out->res = 0;
-    return FEOD_OK;
+    return timed(c, "fill", [&] { return launch_fill(x, 0.0, N, c->stream); });
   }
-  TRY(timed(c, "axpby", [&] { return launch_axpby(r, 1.0, b, 0.0, nullptr, N, c->stream); }));
-  TRY(timed(c, "fill", [&] { return launch_fill(p, 0.0, N, c->stream); }));
-  TRY(timed(c, "fill", [&] { return launch_fill(q, 0.0, N, c->stream); }));
-  TRY(timed(c, "fill", [&] { return launch_fill(c->d_sc + S_RZ0, 0.0, 1, c->stream); }));
-  TRY(timed(c, "fill", [&] { return launch_fill(c->d_sc + S_PQ, 1.0, 1, c->stream); }));
-  // alpha = 0 update: z = M^{-1} r and rz = r.z, rr = r.r
-  int cur = S_RZ0, nxt = S_RZ1;
-  TRY(timed(c, "cg_update", [&] {
-    return launch_cg_update(x, r, z, p, q, dinv, c->d_sc, S_RZ0, S_PQ, N, c->d_part0, c->d_part1, c->stream);
+  int cur = C_RZ0, nxt = C_RZ1;
+  TRY(timed(c, "cg_init", [&] {
+    return launch_cg_init(x, r, z, p, b, dinv, N, c->cg_part(cur), c->cg_part(C_RR), c->stream);
   }));
-  TRY(timed(c, "reduce_final", [&] {
-    return launch_reduce_final(c->d_part0, kRedBlocks, c->d_sc + cur, 1.0, nullptr, c->stream);
-  }));
-  TRY(timed(c, "axpby", [&] { return launch_axpby(p, 1.0, z, 0.0, nullptr, N, c->stream); }));
   const double tol = rtol * out->bnorm;
-  for (int it = 0; it < max_it; ++it) {
-    if (pa) {
-      TRY(run_element(c, OP_JVP_PA, prec, params(c, nullptr, p, c->d_Y0, nullptr, prec)));
-      TRY(timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, q, nullptr); }));
-    } else {
-      TRY(apply_jvp(c, u, p, q, nullptr, prec, p_override));
-    }
-    TRY(dot(c, p, q, N, c->d_sc + S_PQ));
-    TRY(timed(c, "cg_update", [&] {
-      return launch_cg_update(x, r, z, p, q, dinv, c->d_sc, cur, S_PQ, N, c->d_part0, c->d_part1, c->stream);
-    }));
+  double last_true = out->bnorm;  // x = 0: r = b exactly
+  // rr of the residual whose partials are in slot `slot` (r.r, or r.z = r.r without dinv)
+  auto read_rr = [&](int slot, double* rr, double* pq) -> feod_status {
     TRY(timed(c, "reduce_final", [&] {
-      return launch_reduce_final(c->d_part0, kRedBlocks, c->d_sc + nxt, 1.0, nullptr, c->stream);
+      return launch_reduce_final(c->cg_part(dinv ? C_RR : slot), kCgBlocks, c->d_sc + S_RR, 1.0, nullptr,
+                                 c->stream);
     }));
-    if (dinv)
-      TRY(timed(c, "reduce_final", [&] {
-        return launch_reduce_final(c->d_part1, kRedBlocks, c->d_sc + S_RR, 1.0, nullptr, c->stream);
-      }));
+    double sv[4];
+    TRY(read_scalars(c, 0, 4, sv));
+    *rr = sv[S_RR];
+    *pq = sv[S_PQ];
+    if (!std::isfinite(*rr) || !std::isfinite(*pq)) {
+      out->status = FEOD_ENONFINITE;
+      return fail(c, FEOD_ENONFINITE, "non-finite CG scalar");
+    }
+    return FEOD_OK;
+  };
+  for (int it = 0; it < max_it; ++it) {
+    if (pa)
+      TRY(run_element(c, OP_JVP_PA, prec, params(c, nullptr, p, c->d_Y0, nullptr, prec)));
+    else
+      TRY(run_element(c, OP_JVP, prec, params(c, u, p, c->d_Y0, nullptr, prec, p_override)));
+    TRY(gather_t_dot(c, prec == 1, p, q));
+    TRY(timed(c, "cg_step", [&] {
+      return launch_cg_step(x, r, z, p, q, dinv, c->cg_part(cur), c->cg_part(C_PQ), N, c->cg_part(nxt),
+                            c->cg_part(C_RR), c->d_sc, S_RZ, S_PQ, c->stream);
+    }));
     out->iters = it + 1;
     if ((it + 1) % check_every == 0 || it + 1 == max_it) {
-      double s[4];
-      TRY(read_scalars(c, 0, 4, s));
-      const double rr = dinv ? s[S_RR] : s[nxt];
-      const double pq = s[S_PQ];
-      if (!std::isfinite(rr) || !std::isfinite(pq)) {
-        out->status = FEOD_ENONFINITE;
-        return fail(c, FEOD_ENONFINITE, "non-finite CG scalar");
-      }
+      double rr, pq;
+      TRY(read_rr(nxt, &rr, &pq));
       if (pq <= 0.0) {
         out->status = FEOD_EBREAKDOWN;
         return fail(c, FEOD_EBREAKDOWN, "CG breakdown: p^T J p <= 0");
       }
       out->res = std::sqrt(rr);
+      if (reliable && (out->res <= tol || out->res <= kReliableDrop * last_true)) {
+        // q is free here (consumed by the step): q = J64 x, then r = b - q
+        TRY(apply_jvp(c, u, x, q, nullptr, 0, p_override));
+        TRY(timed(c, "cg_true_residual", [&] {
+          return launch_cg_true_residual(r, z, b, q, dinv, N, c->cg_part(nxt), c->cg_part(C_RR), c->stream);
+        }));
+        out->updates++;
+        TRY(read_rr(nxt, &rr, &pq));
+        out->res = last_true = std::sqrt(rr);
+      }
       if (out->res <= tol) return FEOD_OK;
     }
-    TRY(timed(c, "cg_xpay", [&] { return launch_cg_xpay(p, z, c->d_sc, nxt, cur, N, c->stream); }));
+    TRY(timed(c, "cg_direction",
+              [&] { return launch_cg_direction(p, z, c->cg_part(nxt), c->cg_part(cur), N, c->stream); }));
     std::swap(cur, nxt);
   }
   out->status = FEOD_ENOCONV;
@@ -549,6 +580,7 @@ feod_status feod_bind_workspace(feod_ctx* c, void* dev, size_t bytes) {
   for (int i = 0; i < kNumVec; ++i) c->d_vec[i] = (double*)(w + l.vec + i * vstride);
   c->d_part0 = (double*)(w + l.part0);
   c->d_part1 = (double*)(w + l.part1);
+  c->d_cgpart = (double*)(w + l.cgpart);
   c->d_sc = (double*)(w + l.sc);
   // tables: B, D, w, xi
   std::vector<double> t64;
@@ -863,38 +895,18 @@ feod_status feod_adjoint_gradient(feod_ctx* c, const double* u, const double* g_
     rep.res_final = cr.res;
     if (cr.status != FEOD_OK) return finish(fail(c, cr.status, "adjoint CG did not converge"));
   } else {
-    // iterative refinement: FP64 residual, FP32 Jacobian inside CG
-    double* res = c->d_vec[V_R];
-    double* d = c->d_vec[V_UT];
-    double* jx = c->d_vec[V_AUX2];
-    if (feod_status s = timed(c, "fill", [&] { return launch_fill(lam, 0.0, N, c->stream); }); s != FEOD_OK)
+    // FP32 Jacobian applies inside one CG, FP64 vectors, reliable updates
+    // with the FP64 true residual (convergence is decided on it)
+    if (feod_status s = cg(c, u, rhs, lam, o.rtol, o.max_cg, o.check_every, 1, dinv, &cr, 0.0, o.partial_assembly,
+                           /*reliable=*/true);
+        s != FEOD_OK)
       return finish(s);
-    double ref2;
-    if (feod_status s = host_dot(c, rhs, rhs, N, &ref2); s != FEOD_OK) return finish(s);
-    rep.ref_norm = std::sqrt(ref2);
-    for (int k = 0;; ++k) {
-      if (feod_status s = apply_jvp(c, u, lam, jx, nullptr, 0); s != FEOD_OK) return finish(s);
-      if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(res, 1.0, rhs, -1.0, jx, N, c->stream); });
-          s != FEOD_OK)
-        return finish(s);
-      double rn2;
-      if (feod_status s = host_dot(c, res, res, N, &rn2); s != FEOD_OK) return finish(s);
-      const double rn = std::sqrt(rn2);
-      if (!std::isfinite(rn)) return finish(fail(c, FEOD_ENONFINITE, "non-finite refinement residual"));
-      if (k == 0) rep.res0 = rn;
-      rep.res_final = rn;
-      rep.refine_iters = k;
-      if (rn <= o.rtol * rep.ref_norm) break;
-      if (k >= 50) return finish(fail(c, FEOD_ENOCONV, "iterative refinement did not converge"));
-      const double inner = std::max(1e-5, std::min(1e-3, o.rtol * rep.ref_norm / rn));
-      if (feod_status s = cg(c, u, res, d, inner, o.max_cg, o.check_every, 1, dinv, &cr, 0.0, o.partial_assembly);
-          s != FEOD_OK)
-        return finish(s);
-      rep.cg_iters_total += cr.iters;
-      if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(lam, 1.0, lam, 1.0, d, N, c->stream); });
-          s != FEOD_OK)
-        return finish(s);
-    }
+    rep.cg_iters_total = cr.iters;
+    rep.refine_iters = cr.updates;
+    rep.ref_norm = cr.bnorm;
+    rep.res0 = cr.bnorm;
+    rep.res_final = cr.res;
+    if (cr.status != FEOD_OK) return finish(fail(c, cr.status, "adjoint CG did not converge"));
   }
   // The gradient kernel runs in FP64 in both modes: it is one pass, and the
   // refined lambda is FP64-accurate, so the result is too.

@@ -102,15 +102,30 @@ hipError_t launch_dot_partial(const double* x, const double* y, int64_t n, doubl
 hipError_t launch_reduce_final(const double* partial, int nparts, double* out, double sign,
                                const double* add, hipStream_t s);
 
-// CG steps on device-resident scalars (sc = scalar array):
-//   alpha = sc[i_rz] / sc[i_pq]; x += alpha p; r -= alpha q; z = r * dinv (if dinv);
-//   partial0 = r.z (or r.r), partial1 = r.r (if dinv).
-hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* q,
-                            const double* dinv, const double* sc, int i_rz, int i_pq, int64_t n,
-                            double* partial0, double* partial1, hipStream_t s);
-//   beta = sc[i_new] / sc[i_old]; p = z + beta p
-hipError_t launch_cg_xpay(double* p, const double* z, const double* sc, int i_new, int i_old,
-                          int64_t n, hipStream_t s);
+// ---- Fused CG iteration: kCgBlocks blocks, one partial sum per block -----
+constexpr int kCgBlocks = 512;   // partial sums per CG inner product (two blocks per CU)
+constexpr int kCgThreads = 512;  // threads per CG vector block
+constexpr int kCgUnroll = 4;     // DOFs per thread per grid-stride pass
+// q = G^T Y (lattice map when d != null, else the CSR map off/idx) and
+// partial[b] = block b's share of p.q.
+hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
+                               bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s);
+// x = 0, r = b, z = dinv r (z may alias r when dinv is null), p = z, partials of r.z and r.r
+hipError_t launch_cg_init(double* x, double* r, double* z, double* p, const double* b, const double* dinv,
+                          int64_t n, double* part_rz, double* part_rr, hipStream_t s);
+// Reliable update: r = b - jx (the true residual of the current x), z = dinv r,
+// partials of r.z and r.r; x and p are left as they are.
+hipError_t launch_cg_true_residual(double* r, double* z, const double* b, const double* jx, const double* dinv,
+                                   int64_t n, double* part_rz, double* part_rr, hipStream_t s);
+// alpha = sum(part_rz)/sum(part_pq); x += alpha p; r -= alpha q; z = dinv r;
+// new partials of r.z (part_rz_new) and r.r (part_rr, when dinv); block 0
+// stores the two totals in sc[i_rz], sc[i_pq].
+hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
+                          const double* part_rz, const double* part_pq, int64_t n, double* part_rz_new,
+                          double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s);
+// beta = sum(part_new)/sum(part_old); p = z + beta p
+hipError_t launch_cg_direction(double* p, const double* z, const double* part_new, const double* part_old,
+                               int64_t n, hipStream_t s);
 // y = a*x + b*y with host scalars; x or y may alias out
 hipError_t launch_axpby(double* out, double a, const double* x, double b, const double* y,
                         int64_t n, hipStream_t s);
@@ -121,7 +136,7 @@ hipError_t launch_invert_diag(double* dinv, const double* d, int64_t n, hipStrea
 // out[i] = in[i] * (emask[i]) where mask derived from toff rows (interior iff row non-empty)
 hipError_t launch_mask_copy(double* out, const double* in, const int32_t* toff, int64_t n,
                             hipStream_t s);
-// checks: flag[0] = 1 if any x[i] non-finite (writes only on failure)
+// dst[0..count) = src[0..count) on the device (count <= 64)
 hipError_t launch_copy_scalar(double* dst, const double* src, int count, hipStream_t s);
 
 }  // namespace feod

@@ -65,20 +65,15 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
 // lattice lies in element ex = I/k (local a = I%k) and, when I is a multiple
 // of k, also in ex-1 (local a = k); likewise in y and z.  The contributions are
 // summed in ascending element order, which is the order of the explicit map.
-// E-vector layout [ez][ey][c][b][ex][a]: a wavefront of consecutive I reads
-// one contiguous stretch per (element row, c, b).
+// Dirichlet DOFs (on the lattice boundary) get exactly 0.
 template <class TE, bool TWO>
-__global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDims d, const TE* __restrict__ Y0,
-                                                                       const TE* __restrict__ Y1,
-                                                                       const double* __restrict__ bm,
-                                                                       double* __restrict__ out0,
-                                                                       double* __restrict__ out1, int64_t n) {
-  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kVecThreads + threadIdx.x;
-  if (i >= n) return;
+__device__ __forceinline__ void lattice_row_sum(const LatticeDims& d, const TE* __restrict__ Y0,
+                                                const TE* __restrict__ Y1, int64_t i, double& s0, double& s1) {
   // n < 2^31 (checked at set-up): 32-bit unsigned index arithmetic
   const uint32_t iu = (uint32_t)i, t = iu / (uint32_t)d.Lx;
   const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)(t / (uint32_t)d.Ly), J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
-  double s0 = 0, s1 = 0;
+  s0 = 0;
+  s1 = 0;
   if (I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1) {
     const int k = d.k, D1 = k + 1;
     // up to two candidate elements per direction: lower (index/k - 1, local k)
@@ -107,8 +102,20 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDi
       s0 += (double)v0[q];
       if (TWO) s1 += (double)v1[q];
     }
-    if (bm != nullptr) s0 -= bm[i];
   }
+}
+
+template <class TE, bool TWO>
+__global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDims d, const TE* __restrict__ Y0,
+                                                                       const TE* __restrict__ Y1,
+                                                                       const double* __restrict__ bm,
+                                                                       double* __restrict__ out0,
+                                                                       double* __restrict__ out1, int64_t n) {
+  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kVecThreads + threadIdx.x;
+  if (i >= n) return;
+  double s0, s1;
+  lattice_row_sum<TE, TWO>(d, Y0, Y1, i, s0, s1);
+  if (bm != nullptr) s0 -= bm[i];  // bm is 0 on Dirichlet DOFs
   out0[i] = s0;
   if (TWO) out1[i] = s1;
 }
@@ -182,62 +189,6 @@ hipError_t launch_reduce_final(const double* partial, int nparts, double* out, d
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(kVecThreads) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
-                                                                double* __restrict__ z,
-                                                                const double* __restrict__ p,
-                                                                const double* __restrict__ q,
-                                                                const double* __restrict__ dinv,
-                                                                const double* __restrict__ sc, int i_rz,
-                                                                int i_pq, int64_t n, double* partial0,
-                                                                double* partial1) {
-  const double alpha = sc[i_rz] / sc[i_pq];
-  double s0 = 0, s1 = 0;
-  const int64_t stride = (int64_t)kRedBlocks * kVecThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; i < n; i += stride) {
-    x[i] += alpha * p[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
-    if (dinv) {
-      const double zi = ri * dinv[i];
-      z[i] = zi;
-      s0 += ri * zi;
-      s1 += ri * ri;
-    } else {
-      s0 += ri * ri;
-    }
-  }
-  s0 = block_sum(s0);
-  if (threadIdx.x == 0) partial0[blockIdx.x] = s0;
-  if (dinv) {
-    __syncthreads();
-    s1 = block_sum(s1);
-    if (threadIdx.x == 0) partial1[blockIdx.x] = s1;
-  }
-}
-
-hipError_t launch_cg_update(double* x, double* r, double* z, const double* p, const double* q,
-                            const double* dinv, const double* sc, int i_rz, int i_pq, int64_t n,
-                            double* partial0, double* partial1, hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(kRedBlocks), dim3(kVecThreads), 0, s, x, r, z, p, q, dinv, sc,
-                     i_rz, i_pq, n, partial0, partial1);
-  return hipGetLastError();
-}
-
-__global__ __launch_bounds__(kVecThreads) void cg_xpay_kernel(double* __restrict__ p, const double* __restrict__ z,
-                                                              const double* __restrict__ sc, int i_new,
-                                                              int i_old, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
-  if (i >= n) return;
-  const double beta = sc[i_new] / sc[i_old];
-  p[i] = z[i] + beta * p[i];
-}
-
-hipError_t launch_cg_xpay(double* p, const double* z, const double* sc, int i_new, int i_old, int64_t n,
-                          hipStream_t s) {
-  hipLaunchKernelGGL(cg_xpay_kernel, dim3(vec_blocks(n)), dim3(kVecThreads), 0, s, p, z, sc, i_new, i_old, n);
-  return hipGetLastError();
-}
-
 __global__ __launch_bounds__(kVecThreads) void axpby_kernel(double* out, double a, const double* x, double b,
                                                             const double* y, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * kVecThreads + threadIdx.x;
@@ -289,6 +240,301 @@ __global__ void copy_scalar_kernel(double* dst, const double* src, int count) {
 
 hipError_t launch_copy_scalar(double* dst, const double* src, int count, hipStream_t s) {
   hipLaunchKernelGGL(copy_scalar_kernel, dim3(1), dim3(64), 0, s, dst, src, count);
+  return hipGetLastError();
+}
+
+// ---- Fused CG iteration --------------------------------------------------
+// The CG vector kernels run kCgBlocks blocks of kCgThreads (one block per CU)
+// over a grid-stride loop.  Every inner product leaves kCgBlocks partial sums;
+// a kernel that needs the total sums the partials itself, each block in the
+// same fixed order, so all blocks use the bitwise-same scalar and no separate
+// single-block reduction launch (or cross-block fence) is needed.
+static_assert(kCgThreads % 64 == 0, "CG blocks are whole wavefronts");
+
+// Sum of v over the block, returned in every thread; fixed order.
+__device__ __forceinline__ double cg_block_sum(double v, double* ws) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int i = 0; i < kCgThreads / 64; ++i) s += ws[i];
+  __syncthreads();  // ws may be reused
+  return s;
+}
+
+__device__ __forceinline__ double cg_total(const double* __restrict__ part, double* ws) {
+  double v = 0;
+  for (int i = threadIdx.x; i < kCgBlocks; i += kCgThreads) v += part[i];
+  return cg_block_sum(v, ws);
+}
+
+// The grid-stride kernels below take kCgUnroll DOFs per thread per pass (i,
+// i + stride, ...) and issue all their loads before any store: indices past
+// the end are clamped to n-1 for the loads and skipped for stores and sums.
+// Each thread still adds its DOFs in ascending order.
+
+// q = G^T Y and partial[b] = sum of p[i] q[i] over block b's share.
+template <class TE>
+__global__ __launch_bounds__(kCgThreads) void gather_t_lattice_dot_kernel(LatticeDims d, const TE* __restrict__ Y,
+                                                                          const double* __restrict__ p,
+                                                                          double* __restrict__ q, int64_t n,
+                                                                          double* __restrict__ partial) {
+  __shared__ double ws[kCgThreads / 64];
+  double acc = 0;
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  for (int64_t i0 = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i0 < n; i0 += kCgUnroll * stride) {
+    double s[kCgUnroll], pv[kCgUnroll], unused;
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = min(i0 + u * stride, n - 1);
+      lattice_row_sum<TE, false>(d, Y, nullptr, i, s[u], unused);
+      pv[u] = p[i];
+    }
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+        q[i] = s[u];
+        acc += pv[u] * s[u];
+      }
+    }
+  }
+  acc = cg_block_sum(acc, ws);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+template <class TE>
+__global__ __launch_bounds__(kCgThreads) void gather_t_dot_kernel(const int32_t* __restrict__ off,
+                                                                  const int32_t* __restrict__ idx,
+                                                                  const TE* __restrict__ Y,
+                                                                  const double* __restrict__ p,
+                                                                  double* __restrict__ q, int64_t n,
+                                                                  double* __restrict__ partial) {
+  __shared__ double ws[kCgThreads / 64];
+  double acc = 0;
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += stride) {
+    double s = 0;
+    for (int j = off[i]; j < off[i + 1]; ++j) s += (double)Y[idx[j]];
+    q[i] = s;
+    acc += p[i] * s;
+  }
+  acc = cg_block_sum(acc, ws);
+  if (threadIdx.x == 0) partial[blockIdx.x] = acc;
+}
+
+hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
+                               bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s) {
+  const dim3 g(kCgBlocks), b(kCgThreads);
+  if (d) {
+    if (fp32)
+      hipLaunchKernelGGL((gather_t_lattice_dot_kernel<float>), g, b, 0, s, *d, (const float*)Y, p, q, n, partial);
+    else
+      hipLaunchKernelGGL((gather_t_lattice_dot_kernel<double>), g, b, 0, s, *d, (const double*)Y, p, q, n, partial);
+  } else {
+    if (fp32)
+      hipLaunchKernelGGL((gather_t_dot_kernel<float>), g, b, 0, s, off, idx, (const float*)Y, p, q, n, partial);
+    else
+      hipLaunchKernelGGL((gather_t_dot_kernel<double>), g, b, 0, s, off, idx, (const double*)Y, p, q, n, partial);
+  }
+  return hipGetLastError();
+}
+
+// x = 0, r = b, z = dinv r (z aliases r when dinv is null), p = z;
+// part_rz = partials of r.z, part_rr = partials of r.r (when dinv).
+__global__ __launch_bounds__(kCgThreads) void cg_init_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                             double* __restrict__ z, double* __restrict__ p,
+                                                             const double* __restrict__ b,
+                                                             const double* __restrict__ dinv, int64_t n,
+                                                             double* __restrict__ part_rz,
+                                                             double* __restrict__ part_rr) {
+  __shared__ double ws[kCgThreads / 64];
+  double s0 = 0, s1 = 0;
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += stride) {
+    const double ri = b[i];
+    x[i] = 0.0;
+    r[i] = ri;
+    if (dinv) {
+      const double zi = ri * dinv[i];
+      z[i] = zi;
+      p[i] = zi;
+      s0 += ri * zi;
+      s1 += ri * ri;
+    } else {
+      p[i] = ri;
+      s0 += ri * ri;
+    }
+  }
+  s0 = cg_block_sum(s0, ws);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s0;
+  if (dinv) {
+    s1 = cg_block_sum(s1, ws);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s1;
+  }
+}
+
+hipError_t launch_cg_init(double* x, double* r, double* z, double* p, const double* b, const double* dinv,
+                          int64_t n, double* part_rz, double* part_rr, hipStream_t s) {
+  hipLaunchKernelGGL(cg_init_kernel, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, z, p, b, dinv, n, part_rz,
+                     part_rr);
+  return hipGetLastError();
+}
+
+// r = b - jx, z = dinv r; partials of r.z and r.r (x and p unchanged)
+template <bool PREC>
+__global__ __launch_bounds__(kCgThreads) void cg_true_residual_kernel(double* __restrict__ r, double* __restrict__ z,
+                                                                      const double* __restrict__ b,
+                                                                      const double* __restrict__ jx,
+                                                                      const double* __restrict__ dinv, int64_t n,
+                                                                      double* __restrict__ part_rz,
+                                                                      double* __restrict__ part_rr) {
+  __shared__ double ws[kCgThreads / 64];
+  double s0 = 0, s1 = 0;
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += stride) {
+    const double ri = b[i] - jx[i];
+    r[i] = ri;
+    if (PREC) {
+      const double zi = ri * dinv[i];
+      z[i] = zi;
+      s0 += ri * zi;
+      s1 += ri * ri;
+    } else {
+      s0 += ri * ri;
+    }
+  }
+  s0 = cg_block_sum(s0, ws);
+  if (threadIdx.x == 0) part_rz[blockIdx.x] = s0;
+  if (PREC) {
+    s1 = cg_block_sum(s1, ws);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s1;
+  }
+}
+
+hipError_t launch_cg_true_residual(double* r, double* z, const double* b, const double* jx, const double* dinv,
+                                   int64_t n, double* part_rz, double* part_rr, hipStream_t s) {
+  if (dinv)
+    hipLaunchKernelGGL(cg_true_residual_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, r, z, b, jx, dinv, n,
+                       part_rz, part_rr);
+  else
+    hipLaunchKernelGGL(cg_true_residual_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, r, r, b, jx,
+                       nullptr, n, part_rz, nullptr);
+  return hipGetLastError();
+}
+
+// alpha = (r.z) / (p.q) from the partials; x += alpha p; r -= alpha q;
+// z = dinv r; new partials of r.z and r.r.  Block 0 records r.z and p.q in
+// sc[i_rz], sc[i_pq] for the host's convergence and breakdown checks.
+template <bool PREC>
+__global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                             double* __restrict__ z, const double* __restrict__ p,
+                                                             const double* __restrict__ q,
+                                                             const double* __restrict__ dinv,
+                                                             const double* __restrict__ part_rz,
+                                                             const double* __restrict__ part_pq, int64_t n,
+                                                             double* __restrict__ part_rz_new,
+                                                             double* __restrict__ part_rr, double* __restrict__ sc,
+                                                             int i_rz, int i_pq) {
+  __shared__ double ws[kCgThreads / 64];
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  const int64_t first = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
+  // the first pass's loads go out before the scalar sums, hiding their latency
+  double xv[kCgUnroll], pv[kCgUnroll], rv[kCgUnroll], qv[kCgUnroll], dv[kCgUnroll];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = min(i0 + u * stride, n - 1);
+      xv[u] = x[i];
+      pv[u] = p[i];
+      rv[u] = r[i];
+      qv[u] = q[i];
+      if (PREC) dv[u] = dinv[i];
+    }
+  };
+  if (first < n) load(first);
+  const double rz = cg_total(part_rz, ws), pq = cg_total(part_pq, ws);
+  const double alpha = rz / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc[i_rz] = rz;
+    sc[i_pq] = pq;
+  }
+  double s0 = 0, s1 = 0;
+  for (int64_t i0 = first; i0 < n; i0 += kCgUnroll * stride) {
+    if (i0 != first) load(i0);
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) {
+        x[i] = xv[u] + alpha * pv[u];
+        const double ri = rv[u] - alpha * qv[u];
+        r[i] = ri;
+        if (PREC) {
+          const double zi = ri * dv[u];
+          z[i] = zi;
+          s0 += ri * zi;
+          s1 += ri * ri;
+        } else {
+          s0 += ri * ri;
+        }
+      }
+    }
+  }
+  s0 = cg_block_sum(s0, ws);
+  if (threadIdx.x == 0) part_rz_new[blockIdx.x] = s0;
+  if (PREC) {
+    s1 = cg_block_sum(s1, ws);
+    if (threadIdx.x == 0) part_rr[blockIdx.x] = s1;
+  }
+}
+
+hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
+                          const double* part_rz, const double* part_pq, int64_t n, double* part_rz_new,
+                          double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s) {
+  if (dinv)
+    hipLaunchKernelGGL(cg_step_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, z, p, q, dinv, part_rz,
+                       part_pq, n, part_rz_new, part_rr, sc, i_rz, i_pq);
+  else
+    hipLaunchKernelGGL(cg_step_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, r, p, q, nullptr,
+                       part_rz, part_pq, n, part_rz_new, nullptr, sc, i_rz, i_pq);
+  return hipGetLastError();
+}
+
+// beta = (r.z)_new / (r.z)_old from the partials; p = z + beta p.
+__global__ __launch_bounds__(kCgThreads) void cg_direction_kernel(double* __restrict__ p,
+                                                                  const double* __restrict__ z,
+                                                                  const double* __restrict__ part_new,
+                                                                  const double* __restrict__ part_old, int64_t n) {
+  __shared__ double ws[kCgThreads / 64];
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  const int64_t first = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
+  double zv[kCgUnroll], pv[kCgUnroll];
+  auto load = [&](int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = min(i0 + u * stride, n - 1);
+      zv[u] = z[i];
+      pv[u] = p[i];
+    }
+  };
+  if (first < n) load(first);
+  const double beta = cg_total(part_new, ws) / cg_total(part_old, ws);
+  for (int64_t i0 = first; i0 < n; i0 += kCgUnroll * stride) {
+    if (i0 != first) load(i0);
+#pragma unroll
+    for (int u = 0; u < kCgUnroll; ++u) {
+      const int64_t i = i0 + u * stride;
+      if (i < n) p[i] = zv[u] + beta * pv[u];
+    }
+  }
+}
+
+hipError_t launch_cg_direction(double* p, const double* z, const double* part_new, const double* part_old,
+                               int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(kCgBlocks), dim3(kCgThreads), 0, s, p, z, part_new, part_old, n);
   return hipGetLastError();
 }
 

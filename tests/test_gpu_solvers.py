@@ -48,6 +48,17 @@ def test_adjoint_matches_oracle():
         print(prec, rep, relerr(host(grad), grad_o))
         assert relerr(host(lam), lam_o) <= 1e-10
         assert relerr(host(grad), grad_o) <= 1e-10
+        # mixed: the reported residual is the FP64 true residual M g_u - J lambda,
+        # reached through reliable updates (FP64 CG reports its recursive one)
+        jl = prob.jacobian_apply(u, lam)
+        true_res = np.linalg.norm(ora.mask * ora.b - host(jl))
+        ref = np.linalg.norm(ora.mask * ora.b)
+        if prec == "mixed":
+            assert rep["refine_iters"] >= 1
+            assert true_res <= 1e-13 * ref * (1 + 1e-6)
+            assert abs(true_res - rep["res_final"]) <= 1e-6 * rep["res_final"]
+        else:
+            assert true_res <= 1e-12 * ref
 
 
 def test_design_solve_autograd_vs_finite_differences_c4():
