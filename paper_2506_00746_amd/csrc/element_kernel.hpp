@@ -51,11 +51,18 @@ struct Config {
   // SEQ: the two input fields of a Jacobian action pass through the x-pass
   // buffer one after the other (halves it); needs one phase-C line per thread.
   static constexpr bool SEQ = false;
+  // ALIAS2: two-field operations share one LDS region between the phases
+  // (see Lds); one-field operations always do.
+  static constexpr bool ALIAS2 = true;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
   static constexpr int NT = 256;
   static constexpr int EB = 3;
   static constexpr bool SEQ = true;
+  // The two-field kernels hold two fields' gradients at 9 points per thread
+  // (over 168 VGPRs in FP64): registers, not LDS, bound their occupancy, so a
+  // shared region would only add barriers (measured slower).
+  static constexpr bool ALIAS2 = false;
 };
 
 // Loops over a table index are fully unrolled for small D1/NQ (table entries
@@ -69,14 +76,24 @@ struct Unroll {
 // LDS layout.  The x-pass buffer is [c][qx][b]; when D1 is a multiple of 8
 // its qx stride is padded by one scalar, otherwise the NQ distinct qx columns
 // phase C reads at once would fall on only two LDS banks.
-template <int D1, int NQ, int XB, int HF>
+//
+// The x-pass outputs (read in phase C), the z-back outputs (written in C, read
+// in D) and the y-back outputs (written in D, read in E) share one region per
+// element: phases C and D first read what they need into registers, pass a
+// barrier, then write.  This roughly halves the LDS per element, and LDS is
+// what limits the number of resident workgroups.
+template <int D1, int NQ, int XB, int HF, bool SHARE>
 struct Lds {
   static constexpr int XQ = D1 % 8 ? D1 : D1 + 1;  // qx stride
   static constexpr int XC = NQ * XQ;              // c stride
   static constexpr int XS = D1 * XC;              // one x-pass output block [c][qx][b]
   static constexpr int X = XB * XS;               // XB blocks: x-pass outputs, later y-back outputs
   static constexpr int H = HF * D1 * NQ * NQ;     // HF z-back fields [h][c][qy][qx]
-  static constexpr int per_elem = X + H + 24;
+  static constexpr bool ALIAS = SHARE;
+  static constexpr int XSTR = ALIAS ? (X > H ? X : H) : X;  // per-element stride of the x / y-back blocks
+  static constexpr int HSTR = ALIAS ? XSTR : H;             // per-element stride of the z-back block
+  static constexpr int HOFF = ALIAS ? 0 : X;                // z-back region offset, in units of EB
+  static constexpr int region = ALIAS ? XSTR : X + H;       // per element, without the vertices
 };
 
 // Deterministic sum of n LDS values by one wavefront (fixed order).
@@ -197,12 +214,13 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   // (the symmetric tensor terms); y-back blocks: 2 per output, 3 for the diagonal
   constexpr int HF = DIAG ? 6 : 3 * O;
   constexpr int KB = DIAG ? 3 : 2 * O;
-  using L = Lds<D1, NQ, (2 * FX > KB ? 2 * FX : KB), HF>;
-  __shared__ T smem[EB * L::per_elem];
+  using L = Lds<D1, NQ, (2 * FX > KB ? 2 * FX : KB), HF, (F == 1 || C::ALIAS2)>;
+  static_assert(EB * NQ2 <= NT && EB * D1 * NQ <= NT, "phases C and D take one line per thread");
+  __shared__ T smem[EB * (L::region + 24)];
   __shared__ T sB[NQ * L::XQ], sD[NQ * L::XQ];  // table rows, same padded stride
-  T* Xs = smem;                 // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
-  T* Hs = Xs + EB * L::X;       // [el][o][d][c][qy][qx]; per-line sums for reductions
-  T* Vs = Hs + EB * L::H;       // [el][24] vertex coordinates
+  T* Xs = smem;                     // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
+  T* Hs = smem + EB * L::HOFF;      // [el][o][d][c][qy][qx]; per-line sums for reductions
+  T* Vs = smem + EB * L::region;    // [el][24] vertex coordinates
 
   const int tid = threadIdx.x;
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EB;
@@ -240,13 +258,13 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   // ---- A: gather + x-pass ---------------------------------------------------
   if constexpr (PA) {
     const double* const src[1] = {P.v};
-    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
   } else if constexpr (F == 2 && !SEQ) {
     const double* const src[2] = {P.u, P.v};
-    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
   } else {
     const double* const src[1] = {P.u};
-    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
   }
   __syncthreads();
 
@@ -265,16 +283,18 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
         By[b] = sB[qy * L::XQ + b];
         Dy[b] = sD[qy * L::XQ + b];
       }
-      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[0]);
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR, By, Dy, qx, g[0]);
     }
     __syncthreads();
     const double* const src[1] = {P.v};
-    phase_a<D1, NQ, EB, NT, L::X, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
     __syncthreads();
   }
-  for (int l = tid; l < EB * NQ2; l += NT) {
-    const int el = l / NQ2, qxy = l - el * NQ2;
-    const int qy = qxy / NQ, qx = qxy - qy * NQ;
+  const int l = tid;  // one column per thread
+  const bool active = l < EB * NQ2;
+  const int el = active ? l / NQ2 : 0, qxy = active ? l - el * NQ2 : 0;
+  const int qy = qxy / NQ, qx = qxy - qy * NQ;
+  if (active) {
     T By[D1], Dy[D1];
 #pragma unroll
     for (int b = 0; b < D1; ++b) {
@@ -282,7 +302,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       Dy[b] = sD[qy * L::XQ + b];
     }
     if constexpr (QSTORE) {
-      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[0]);
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR, By, Dy, qx, g[0]);
       if (el < n_valid) {
         T* qd = static_cast<T*>(P.qdata) + (int64_t)(e0 + el) * 3 * NQ * NQ2 + qxy;
 #pragma unroll
@@ -290,21 +310,23 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
 #pragma unroll
           for (int qz = 0; qz < NQ; ++qz) qd[(d * NQ + qz) * NQ2] = g[0][d][qz];
       }
-      continue;
     } else if constexpr (PA) {
       // v from the x-pass buffer; u's reference gradients from the stored data
-      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[1]);
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR, By, Dy, qx, g[1]);
       const T* qd = static_cast<const T*>(P.qdata) + (int64_t)(e0 + (el < n_valid ? el : 0)) * 3 * NQ * NQ2 + qxy;
 #pragma unroll
       for (int d = 0; d < 3; ++d)
 #pragma unroll
         for (int qz = 0; qz < NQ; ++qz) g[0][d][qz] = qd[(d * NQ + qz) * NQ2];
     } else if constexpr (SEQ) {
-      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X, By, Dy, qx, g[1]);
+      column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR, By, Dy, qx, g[1]);
     } else {
 #pragma unroll
-      for (int f = 0; f < F; ++f) column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::X + f * 2 * L::XS, By, Dy, qx, g[f]);
+      for (int f = 0; f < F; ++f) column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR + f * 2 * L::XS, By, Dy, qx, g[f]);
     }
+  }
+  if (L::ALIAS) __syncthreads();  // x-pass buffer consumed: the z-back may overwrite it
+  if (active && !QSTORE) {
     const bool valid = el < n_valid;
     const T rho = (P.rho != nullptr && valid) ? (T)P.rho[e0 + el] : T(1);
     const T wxy = tb.w[qx] * tb.w[qy];
@@ -449,7 +471,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       Hs[l] = (T)part;
     } else if constexpr (DIAG) {
       // z factors of the six terms: B^2 (00, 11, 01), D^2 (22), B D (02, 12)
-      T* h = Hs + el * L::H + qxy;
+      T* h = Hs + el * L::HSTR + qxy;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
       for (int c = 0; c < D1; ++c) {
         T s[6] = {0, 0, 0, 0, 0, 0};
@@ -471,7 +493,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       // z-back: H0[c] = sum_qz B Fx, H1 = sum_qz B Fy, H2 = sum_qz D Fz
 #pragma unroll
       for (int o = 0; o < O; ++o) {
-        T* h = Hs + el * L::H + o * 3 * D1 * NQ2 + qxy;
+        T* h = Hs + el * L::HSTR + o * 3 * D1 * NQ2 + qxy;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
         for (int c = 0; c < D1; ++c) {
           T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.D[c] * g[o][2][0];
@@ -502,61 +524,64 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   }
 
   // ---- D: y-back: K0[b] = sum_qy B H0 ; K1[b] = sum_qy (D H1 + B H2) -> K ------
-  for (int l = tid; l < EB * D1 * NQ; l += NT) {
-    const int el = l / (D1 * NQ), rem = l - el * (D1 * NQ);
+  {
+    const int l = tid;  // one line (c, qx) per thread
+    const bool active = l < EB * D1 * NQ;
+    const int el = active ? l / (D1 * NQ) : 0, rem = active ? l - el * (D1 * NQ) : 0;
     const int c = rem / NQ, qx = rem - c * NQ;
-    if constexpr (DIAG) {
-      // group by x factor: K_D2 (term 00), K_B2 (11, 22, 12), K_DB (01, 02)
-      const T* h = Hs + el * L::H + c * NQ2 + qx;
-      T hv[6][NQ];
+    constexpr int NH = DIAG ? 6 : 3 * O;  // z-back fields read by this line
+    T hv[NH][NQ];
+    if (active) {
+      const T* h = Hs + el * L::HSTR + c * NQ2 + qx;
 #pragma unroll
-      for (int t = 0; t < 6; ++t)
+      for (int t = 0; t < NH; ++t)
 #pragma unroll
         for (int qy = 0; qy < NQ; ++qy) hv[t][qy] = h[t * D1 * NQ2 + qy * NQ];
-      T* k = Xs + el * L::X + (c * NQ + qx) * L::XQ;
-#pragma unroll(Unroll<D1>::full ? D1 : 1)
-      for (int b = 0; b < D1; ++b) {
-        T kd2 = 0, kb2 = 0, kdb = 0;
-#pragma unroll
-        for (int qy = 0; qy < NQ; ++qy) {
-          const T by = tb.B[qy * D1 + b], dy = tb.D[qy * D1 + b];
-          const T bb = by * by, dd = dy * dy, bd = by * dy;
-          kd2 += bb * hv[0][qy];
-          kb2 += dd * hv[1][qy];
-          kb2 += bb * hv[2][qy];
-          kb2 += bd * hv[5][qy];
-          kdb += bd * hv[3][qy];
-          kdb += bb * hv[4][qy];
-        }
-        k[b] = kd2;
-        k[L::XS + b] = kb2;
-        k[2 * L::XS + b] = kdb;
-      }
-      continue;
     }
-#pragma unroll
-    for (int o = 0; o < O; ++o) {
-      const T* h = Hs + el * L::H + o * 3 * D1 * NQ2 + c * NQ2 + qx;
-      T h0[NQ], h1[NQ], h2[NQ];
-#pragma unroll
-      for (int qy = 0; qy < NQ; ++qy) {
-        h0[qy] = h[qy * NQ];
-        h1[qy] = h[D1 * NQ2 + qy * NQ];
-        h2[qy] = h[2 * D1 * NQ2 + qy * NQ];
-      }
-      T* k = Xs + el * L::X + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
+    if (L::ALIAS) __syncthreads();  // z-back buffer consumed: the y-back may overwrite it
+    if (active) {
+      if constexpr (DIAG) {
+        // group by x factor: K_D2 (term 00), K_B2 (11, 22, 12), K_DB (01, 02)
+        T* k = Xs + el * L::XSTR + (c * NQ + qx) * L::XQ;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
-      for (int b = 0; b < D1; ++b) {
-        T s0 = tb.B[b] * h0[0], s1 = tb.D[b] * h1[0];
-        s1 += tb.B[b] * h2[0];
+        for (int b = 0; b < D1; ++b) {
+          T kd2 = 0, kb2 = 0, kdb = 0;
 #pragma unroll
-        for (int qy = 1; qy < NQ; ++qy) {
-          s0 += tb.B[qy * D1 + b] * h0[qy];
-          s1 += tb.D[qy * D1 + b] * h1[qy];
-          s1 += tb.B[qy * D1 + b] * h2[qy];
+          for (int qy = 0; qy < NQ; ++qy) {
+            const T by = tb.B[qy * D1 + b], dy = tb.D[qy * D1 + b];
+            const T bb = by * by, dd = dy * dy, bd = by * dy;
+            kd2 += bb * hv[0][qy];
+            kb2 += dd * hv[1][qy];
+            kb2 += bb * hv[2][qy];
+            kb2 += bd * hv[5][qy];
+            kdb += bd * hv[3][qy];
+            kdb += bb * hv[4][qy];
+          }
+          k[b] = kd2;
+          k[L::XS + b] = kb2;
+          k[2 * L::XS + b] = kdb;
         }
-        k[b] = s0;
-        k[L::XS + b] = s1;
+      } else {
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+          const T(&h0)[NQ] = hv[3 * o];
+          const T(&h1)[NQ] = hv[3 * o + 1];
+          const T(&h2)[NQ] = hv[3 * o + 2];
+          T* k = Xs + el * L::XSTR + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
+#pragma unroll(Unroll<D1>::full ? D1 : 1)
+          for (int b = 0; b < D1; ++b) {
+            T s0 = tb.B[b] * h0[0], s1 = tb.D[b] * h1[0];
+            s1 += tb.B[b] * h2[0];
+#pragma unroll
+            for (int qy = 1; qy < NQ; ++qy) {
+              s0 += tb.B[qy * D1 + b] * h0[qy];
+              s1 += tb.D[qy * D1 + b] * h1[qy];
+              s1 += tb.B[qy * D1 + b] * h2[qy];
+            }
+            k[b] = s0;
+            k[L::XS + b] = s1;
+          }
+        }
       }
     }
   }
@@ -577,7 +602,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
     const int64_t pos = (int64_t)(e0 + el) * Ne + cb * D1;
 #endif
     if constexpr (DIAG) {
-      const T* k = Xs + el * L::X + c * L::XC + b;
+      const T* k = Xs + el * L::XSTR + c * L::XC + b;
       T kd2[NQ], kb2[NQ], kdb[NQ];
 #pragma unroll
       for (int qx = 0; qx < NQ; ++qx) {
@@ -602,7 +627,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
     }
 #pragma unroll
     for (int o = 0; o < O; ++o) {
-      const T* k = Xs + el * L::X + o * 2 * L::XS + c * L::XC + b;
+      const T* k = Xs + el * L::XSTR + o * 2 * L::XS + c * L::XC + b;
       T k0[NQ], k1[NQ];
 #pragma unroll
       for (int qx = 0; qx < NQ; ++qx) {
