@@ -8,7 +8,9 @@ resident in HBM.  value = n_dofs * steps / elapsed / 1e9 (GDOF/s) on the
 Also reported on the same JSON line (each timed separately, none of it part
 of ``value``): the mixed-precision Jacobian apply, the residual, the fused
 residual + Jacobian apply, the same applies on the other workloads, the
-Newton-CG and adjoint-gradient times on the design workload, the roofline of
+Newton-CG and adjoint-gradient times (wall and kernel sum), the element
+tangent matrices, partial assembly, single applies with the Infinity Cache
+flushed, the mixed-precision error at random and smooth inputs, the roofline of
 the dominant (element) kernel, whose duration is timed with events over
 back-to-back launches of the element stage alone on the library's stream,
 its HBM traffic from the committed rocprofv3 summary (when measured on the
@@ -169,6 +171,11 @@ def solve_rows(feod, WORKLOADS, make_inputs, dev):
                         g_ref = g.clone()
                     else:
                         row["grad_rel_diff_vs_fp64"] = float(torch.linalg.norm(g - g_ref) / torch.linalg.norm(g_ref))
+                    # the same solve again with every launch timed by events: GPU kernel time
+                    pb.profile(True)
+                    pb.adjoint_gradient(u_ref, b, rtol=1e-10, prec=prec, partial_assembly=pa)
+                    row["kernel_sum_ms"] = sum(ms for _, ms in pb.profile_read().values())
+                    pb.profile(False)
                     out[f"c4_adjoint_gradient_{prec}_pa{pa}"] = row
         del pb
         torch.cuda.empty_cache()
@@ -235,6 +242,79 @@ def partial_assembly_rows(feod, WORKLOADS, make_inputs, dev, args):
         out[name] = row
         log(f"[bench] partial assembly {name}: {row}")
         del pb, u, v, jv
+        torch.cuda.empty_cache()
+    return out
+
+
+def mall_cold_rows(feod, WORKLOADS, make_inputs, dev, reps=21):
+    """Single FP64 Jacobian applies with the 256 MB Infinity Cache flushed
+    before each (a 1 GiB buffer is written between applies, outside the timed
+    window), against the warm back-to-back rate and a measured device-copy
+    bandwidth.  Bytes are the apply's algorithmic bytes: element kernel (unique
+    L-vector reads, E-vector write) plus G^T (E-vector read, L-vector write)."""
+    import torch
+    flush = torch.empty(128 * 1024 * 1024, dtype=torch.float64, device=dev)
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    copy_ms = timed_loop(lambda: dst.copy_(src), 10, 2)
+    copy_gbs = 2 * src.numel() * 8 / (copy_ms * 1e-3) / 1e9
+    del src, dst
+    s = torch.cuda.Event(enable_timing=True)
+    e = torch.cuda.Event(enable_timing=True)
+    out = {"copy_GBs": copy_gbs}
+    for name in ("c2", "c4", "c5"):
+        w = WORKLOADS[name]
+        ii = make_inputs(w)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=ii["vertices"], rho=ii["rho"],
+                          device=dev)
+        u = torch.as_tensor(ii["u"], device=dev)
+        v = torch.as_tensor(ii["v"], device=dev)
+        jv = torch.empty_like(u)
+        warm = timed_loop(lambda: pb.jacobian_apply(u, v, out=jv), 50, 5)
+        times = []
+        for i in range(reps + 2):
+            flush.fill_(float(i))
+            s.record()
+            pb.jacobian_apply(u, v, out=jv)
+            e.record()
+            torch.cuda.synchronize()
+            if i >= 2:
+                times.append(s.elapsed_time(e))
+        cold = sorted(times)[len(times) // 2]
+        kbytes, _ = pb.kernel_cost("jvp", "fp64")
+        nbytes = kbytes + 8 * w.n_elems * (w.k + 1) ** 3 + 8 * w.n_dofs
+        out[name] = {"cold_us": cold * 1e3, "warm_us": warm * 1e3, "GDOF/s_cold": w.n_dofs / (cold * 1e-3) / 1e9,
+                     "apply_bytes": nbytes, "hbm_frac_cold": nbytes / (cold * 1e-3) / (HBM_PEAK_GBS * 1e9),
+                     "copy_frac_cold": nbytes / (cold * 1e-3) / (copy_gbs * 1e9)}
+        log(f"[bench] MALL-cold {name}: {out[name]}")
+        del pb, u, v, jv
+        torch.cuda.empty_cache()
+    log(f"[bench] device copy {copy_gbs:.0f} GB/s")
+    del flush
+    torch.cuda.empty_cache()
+    return out
+
+
+def mixed_error_rows(feod, WORKLOADS, make_inputs, dev):
+    """Relative L2 difference of the mixed-precision Jacobian apply from the
+    FP64 one, at the seeded random u and at a smooth u (the Newton solution)."""
+    import torch
+    out = {}
+    for name in ("c2", "c4", "c5"):
+        w = WORKLOADS[name]
+        ii = make_inputs(w)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=ii["vertices"], rho=ii["rho"],
+                          device=dev)
+        u = torch.as_tensor(ii["u"], device=dev)
+        v = torch.as_tensor(ii["v"], device=dev)
+        row = {}
+        for tag, uu in (("random_u", u), ("newton_u", pb.newton_solve(rtol=1e-10)[0])):
+            j64 = pb.jacobian_apply(uu, v)
+            j32 = pb.jacobian_apply(uu, v, prec="mixed")
+            row[tag] = float(torch.linalg.norm(j32 - j64) / torch.linalg.norm(j64))
+        out[name] = row
+        log(f"[bench] mixed-vs-FP64 Jacobian apply error {name}: {row}")
+        del pb, u, v
         torch.cuda.empty_cache()
     return out
 
@@ -332,6 +412,8 @@ def main():
         rows["solves"] = solve_rows(feod, WORKLOADS, make_inputs, dev)
         rows["element_tangents"] = tangent_rows(feod, WORKLOADS, make_inputs, dev, args)
         rows["partial_assembly"] = partial_assembly_rows(feod, WORKLOADS, make_inputs, dev, args)
+        rows["mall_cold"] = mall_cold_rows(feod, WORKLOADS, make_inputs, dev)
+        rows["mixed_error"] = mixed_error_rows(feod, WORKLOADS, make_inputs, dev)
 
     cpu = None
     if not args.no_cpu_baseline:
