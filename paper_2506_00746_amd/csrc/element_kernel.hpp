@@ -54,6 +54,11 @@ struct Config {
   // ALIAS2: two-field operations share one LDS region between the phases
   // (see Lds); one-field operations always do.
   static constexpr bool ALIAS2 = true;
+  // WPE: minimum waves per SIMD asked of the register allocator.  At Q4 / nq 6
+  // in FP32 asking for 6 lets the Jacobian kernel fit 67 VGPRs (7 waves) and
+  // runs it 15% faster; elsewhere the default allocation was as fast or
+  // faster (FP64 Q3 spills under the same request).
+  static constexpr int WPE = (D1 == 5 && NQ == 6 && sizeof(T) == 4) ? 6 : 1;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
   static constexpr int NT = 256;
@@ -63,6 +68,7 @@ template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefr
   // (over 168 VGPRs in FP64): registers, not LDS, bound their occupancy, so a
   // shared region would only add barriers (measured slower).
   static constexpr bool ALIAS2 = false;
+  static constexpr int WPE = 1;
 };
 
 // Loops over a table index are fully unrolled for small D1/NQ (table entries
@@ -135,11 +141,16 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
       const int I0 = P.k * sE[el][0], J = P.k * sE[el][1] + b, K = P.k * sE[el][2] + c;
       const bool row = J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
       const int64_t base = I0 + (int64_t)P.Lx * (J + (int64_t)P.Ly * K);
+      // every node of a valid element lies in the lattice: load unconditionally
+      // (no branch per load) and zero the Dirichlet ones
 #pragma unroll
       for (int a = 0; a < D1; ++a) {
         const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) in[f][a] = ok ? (T)src[f][base + a] : T(0);
+        for (int f = 0; f < NF; ++f) {
+          const double val = src[f][base + a];
+          in[f][a] = ok ? (T)val : T(0);
+        }
       }
     } else {
 #pragma unroll
@@ -196,7 +207,8 @@ __device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const 
 }
 
 template <int D1, int NQ, class T, int OP, bool CURVED, int PK>
-__global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
+__global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) void element_kernel(ElemParams P,
+                                                                                                Tab<D1, NQ, T> tb) {
   using C = Config<D1, NQ, T>;
   constexpr int NT = C::NT;
   constexpr int EB = C::EB;
@@ -216,7 +228,8 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   constexpr int KB = DIAG ? 3 : 2 * O;
   using L = Lds<D1, NQ, (2 * FX > KB ? 2 * FX : KB), HF, (F == 1 || C::ALIAS2)>;
   static_assert(EB * NQ2 <= NT && EB * D1 * NQ <= NT, "phases C and D take one line per thread");
-  __shared__ T smem[EB * (L::region + 24)];
+  constexpr int VTX = CURVED ? 24 : 0;  // vertex coordinates per element (curved meshes only)
+  __shared__ T smem[EB * (L::region + VTX)];
   __shared__ T sB[NQ * L::XQ], sD[NQ * L::XQ];  // table rows, same padded stride
   T* Xs = smem;                     // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
   T* Hs = smem + EB * L::HOFF;      // [el][o][d][c][qy][qx]; per-line sums for reductions
@@ -227,11 +240,10 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
   const int n_valid = min(EB, P.E - e0);
   __shared__ int sE[EB][3];  // (ex, ey, ez) of each element of the batch
   if (tid < EB) {
-    const int e = e0 + tid;
-    const int ex = e % P.nx, t = e / P.nx;
-    sE[tid][0] = ex;
-    sE[tid][1] = t % P.ny;
-    sE[tid][2] = t / P.ny;
+    const uint32_t e = (uint32_t)(e0 + tid), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
+    sE[tid][0] = (int)(e - t * (uint32_t)P.nx);
+    sE[tid][1] = (int)(t - z * (uint32_t)P.ny);
+    sE[tid][2] = (int)z;
   }
 
   for (int i = tid; i < NQ * D1; i += NT) {
@@ -244,8 +256,8 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT)) void element_kernel(ElemPa
       const int el = i / 24, r = i - el * 24, vtx = r / 3, al = r - vtx * 3;
       T val = 0;
       if (el < n_valid) {
-        const int e = e0 + el;
-        const int ex = e % P.nx, ey = (e / P.nx) % P.ny, ez = e / (P.nx * P.ny);
+        const uint32_t e = (uint32_t)(e0 + el), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
+        const int ex = (int)(e - t * (uint32_t)P.nx), ey = (int)(t - z * (uint32_t)P.ny), ez = (int)z;
         const int gi = (ex + (vtx & 1)) + (P.nx + 1) * ((ey + ((vtx >> 1) & 1)) + (P.ny + 1) * (ez + (vtx >> 2)));
         val = (T)P.verts[(int64_t)gi * 3 + al];
       }

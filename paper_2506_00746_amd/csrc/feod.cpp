@@ -238,6 +238,8 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
   P.r = (p - 2.0) / 2.0;
   P.inv_p = 1.0 / p;
   P.powkind = pow_kind(p);
+  P.div_nx = make_fastdiv((uint32_t)c->nx);
+  P.div_ny = make_fastdiv((uint32_t)c->ny);
   return P;
 }
 
@@ -257,12 +259,20 @@ feod_status run_element(feod_ctx* c, int op, int prec, const ElemParams& P) {
   return timed(c, op_name(op, prec), [&] { return fn(P, c->stream); });
 }
 
+LatticeDims lattice_dims(const feod_ctx* c) {
+  LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz, {}, {}, {}};
+  d.div_Lx = make_fastdiv((uint32_t)d.Lx);
+  d.div_Ly = make_fastdiv((uint32_t)d.Ly);
+  d.div_k = make_fastdiv((uint32_t)d.k);
+  return d;
+}
+
 // G^T of one or two E-vectors: y0 = G^T Y0 - bm (bm may be null), y1 = G^T Y1
 hipError_t gather_t(feod_ctx* c, const void* Y0, const void* Y1, bool fp32, const double* bm, double* y0,
                     double* y1) {
   if (c->explicit_maps)
     return launch_gather_t(c->d_toff, c->d_tidx, Y0, Y1, fp32, bm, y0, y1, c->lat.N, c->stream);
-  LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz};
+  LatticeDims d = lattice_dims(c);
   return launch_gather_t_lattice(d, Y0, Y1, fp32, bm, y0, y1, c->lat.N, c->stream);
 }
 
@@ -337,7 +347,7 @@ feod_status gather_t_dot(feod_ctx* c, bool fp32, const double* p, double* q) {
     if (c->explicit_maps)
       return launch_gather_t_dot(nullptr, c->d_toff, c->d_tidx, c->d_Y0, fp32, p, q, c->lat.N,
                                  c->cg_part(C_PQ), c->stream);
-    LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz};
+    LatticeDims d = lattice_dims(c);
     return launch_gather_t_dot(&d, nullptr, nullptr, c->d_Y0, fp32, p, q, c->lat.N, c->cg_part(C_PQ), c->stream);
   });
 }

@@ -21,6 +21,24 @@ enum : int {
 };
 
 // Arguments of the fused element kernel (passed by value).
+// Exact division by a runtime divisor d (1 <= d <= 2^31) of numerators
+// n < 2^31 with one 32x32->64-bit multiply and a shift (the round-up
+// multiplier method of Granlund and Montgomery, 1994): with l = ceil(log2 d),
+// m = ceil(2^(31+l) / d) < 2^32 and s = 31 + l, floor(n/d) = (n m) >> s,
+// since n m / 2^s = n/d + delta with 0 <= delta < 2^-l <= 1/d.
+struct FastDiv {
+  uint32_t m, s;
+};
+inline FastDiv make_fastdiv(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;
+  const uint64_t p = uint64_t(1) << (31 + l);
+  return {(uint32_t)((p + d - 1) / d), 31 + l};
+}
+__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
+  return (uint32_t)(((uint64_t)n * f.m) >> f.s);
+}
+
 struct ElemParams {
   const double* u;        // L-vector (FP64)
   const double* v;        // second L-vector: JVP direction or adjoint lambda
@@ -41,6 +59,7 @@ struct ElemParams {
   double sdet[3];         // affine meshes: det * hinv
   double p, eps2, r, inv_p;
   int32_t powkind;
+  FastDiv div_nx, div_ny;  // element index -> (ex, ey, ez)
 };
 
 // Output E-vector layout: 0 (default) = [e][c][b][a], each element's entries
@@ -88,6 +107,7 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
 // Structured lattice of the element-to-DOF map, for the computed G^T.
 struct LatticeDims {
   int32_t nx, ny, nz, k, Lx, Ly, Lz;
+  FastDiv div_Lx, div_Ly, div_k;  // DOF index -> (I, J, K) -> element index
 };
 // Same sums as launch_gather_t, in the same (ascending E-vector position)
 // order, with each DOF's element list computed from the lattice.

@@ -42,7 +42,8 @@ __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, 
     sQ[i] = tb.xi[i];
   }
   const int e = P.e_first + blockIdx.x;
-  const int ex = e % P.nx, ey = (e / P.nx) % P.ny, ez = e / (P.nx * P.ny);
+  const uint32_t et = fastdiv((uint32_t)e, P.div_nx), ez_ = fastdiv(et, P.div_ny);
+  const int ex = (int)((uint32_t)e - et * (uint32_t)P.nx), ey = (int)(et - ez_ * (uint32_t)P.ny), ez = (int)ez_;
 
   // gather M u_e (lattice map; Dirichlet nodes read as 0) and the vertices
   for (int i = tid; i < Ne; i += NT) {

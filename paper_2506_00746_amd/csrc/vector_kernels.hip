@@ -70,15 +70,16 @@ template <class TE, bool TWO>
 __device__ __forceinline__ void lattice_row_sum(const LatticeDims& d, const TE* __restrict__ Y0,
                                                 const TE* __restrict__ Y1, int64_t i, double& s0, double& s1) {
   // n < 2^31 (checked at set-up): 32-bit unsigned index arithmetic
-  const uint32_t iu = (uint32_t)i, t = iu / (uint32_t)d.Lx;
-  const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)(t / (uint32_t)d.Ly), J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
+  const uint32_t iu = (uint32_t)i, t = fastdiv(iu, d.div_Lx);
+  const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)fastdiv(t, d.div_Ly), J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
   s0 = 0;
   s1 = 0;
   if (I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1) {
     const int k = d.k, D1 = k + 1;
     // up to two candidate elements per direction: lower (index/k - 1, local k)
     // when the index is a multiple of k, and upper (index/k, local index%k)
-    const int ix = I / k, iy = J / k, iz = K / k;
+    const int ix = (int)fastdiv((uint32_t)I, d.div_k), iy = (int)fastdiv((uint32_t)J, d.div_k),
+              iz = (int)fastdiv((uint32_t)K, d.div_k);
     const bool lx = I - k * ix == 0, ly = J - k * iy == 0, lz = K - k * iz == 0;
     TE v0[8], v1[8];
 #pragma unroll
