@@ -80,7 +80,10 @@ typedef struct {
 
 /* Newton-CG / adjoint options.  Newton stops when ||R(u)||_2 <= rtol ||M b||_2;
  * the adjoint solve when ||M g_u - J lambda||_2 <= rtol ||M g_u||_2.  CG inner
- * tolerance: eta_j = min(0.1, sqrt(||R_j||/||R_0||)), floored by cg_rtol_floor.
+ * tolerance: eta_j = min(0.1, sqrt(||R_j||/||R_0||)), raised to at least
+ * 0.5 rtol ||M b|| / ||R_j|| (no tighter than the stopping test needs) and
+ * floored by cg_rtol_floor.  The p = 2 initial guess (init_poisson) is a CG
+ * solve to 1e-3 relative.
  * The line search is Armijo backtracking on the energy (c = 1e-4, halving,
  * at most max_ls halvings).  check_every: CG reads its residual norm back to
  * the host every this many iterations.  prec: FEOD_MIXED runs the Jacobian

@@ -293,14 +293,14 @@ feod_status apply_jvp(feod_ctx* c, const double* u, const double* v, double* jv,
 }
 
 // diag(J(u)) = M G^T (element diagonals), boundary rows 0
-feod_status apply_diagonal(feod_ctx* c, const double* u, double* diag, int prec) {
-  TRY(run_element(c, OP_DIAG, prec, params(c, u, nullptr, c->d_Y0, nullptr, prec)));
+feod_status apply_diagonal(feod_ctx* c, const double* u, double* diag, int prec, double p_override = 0.0) {
+  TRY(run_element(c, OP_DIAG, prec, params(c, u, nullptr, c->d_Y0, nullptr, prec, p_override)));
   return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, prec == 1, nullptr, diag, nullptr); });
 }
 
 // dinv = 1 / diag(J(u)) on interior DOFs, 0 on Dirichlet DOFs (Jacobi preconditioner)
-feod_status jacobi(feod_ctx* c, const double* u, double* dinv, double* tmp) {
-  TRY(apply_diagonal(c, u, tmp, 0));
+feod_status jacobi(feod_ctx* c, const double* u, double* dinv, double* tmp, double p_override = 0.0) {
+  TRY(apply_diagonal(c, u, tmp, 0, p_override));
   return timed(c, "invert_diag", [&] { return launch_invert_diag(dinv, tmp, c->lat.N, c->stream); });
 }
 
@@ -411,7 +411,7 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
   };
   for (int it = 0; it < max_it; ++it) {
     if (pa)
-      TRY(run_element(c, OP_JVP_PA, prec, params(c, nullptr, p, c->d_Y0, nullptr, prec)));
+      TRY(run_element(c, OP_JVP_PA, prec, params(c, nullptr, p, c->d_Y0, nullptr, prec, p_override)));
     else
       TRY(run_element(c, OP_JVP, prec, params(c, u, p, c->d_Y0, nullptr, prec, p_override)));
     TRY(gather_t_dot(c, prec == 1, p, q));
@@ -757,6 +757,8 @@ feod_status feod_set_rho(feod_ctx* c, const double* rho_dev) {
   return FEOD_OK;
 }
 
+constexpr double kInitRtol = 1e-3;  // relative CG tolerance of the Poisson initial guess
+
 feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* opts_in,
                               feod_solver_report* rep_out) {
   const auto t0 = std::chrono::steady_clock::now();
@@ -789,7 +791,20 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
     // p = 2: J is the Laplacian, independent of u (linearised at u = 0)
     if (feod_status s = timed(c, "fill", [&] { return launch_fill(u, 0.0, N, c->stream); }); s != FEOD_OK)
       return finish(s);
-    feod_status s = cg(c, u, c->d_bm, ut, 1e-6, o.max_cg, o.check_every, prec, nullptr, &cr, 2.0);
+    const double* dinv0 = nullptr;
+    if (o.jacobi) {
+      if (feod_status s = jacobi(c, u, c->d_vec[V_DINV], ut, 2.0); s != FEOD_OK) return finish(s);
+      dinv0 = c->d_vec[V_DINV];
+    }
+    if (o.partial_assembly) {
+      if (feod_status s = run_element(c, OP_QSTORE, prec, params(c, u, nullptr, nullptr, nullptr, prec)); s != FEOD_OK)
+        return finish(s);
+      c->pa_prec = prec;
+    }
+    // an initial guess only: the first Newton residual is O(1) relative for
+    // these problems, so the Poisson solve is not carried below 1e-3
+    feod_status s = cg(c, u, c->d_bm, ut, kInitRtol, o.max_cg, o.check_every, prec, dinv0, &cr, 2.0,
+                       o.partial_assembly);
     if (s != FEOD_OK) return finish(s);
     rep.cg_iters_total += cr.iters;
     if (feod_status s2 = timed(c, "axpby", [&] { return launch_axpby(u, 1.0, ut, 0.0, nullptr, N, c->stream); });
@@ -811,7 +826,11 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
     rep.newton_iters = it;
     if (nr <= o.rtol * rep.ref_norm) return finish(FEOD_OK);
     if (it >= o.max_newton) return finish(fail(c, FEOD_ENOCONV, "Newton iteration cap reached"));
+    // forcing: eta = min(0.1, sqrt(|R_j| / |R_0|)), but never tighter than
+    // the final tolerance needs (safeguard 0.5 tol |Mb| / |R_j|: a step that
+    // reduces |R| by eta reaches the stopping test), floored at cg_rtol_floor
     double eta = std::min(0.1, std::sqrt(nr / rep.res0));
+    eta = std::max(eta, 0.5 * o.rtol * rep.ref_norm / nr);
     eta = std::max(eta, o.cg_rtol_floor);
     if (feod_status s = timed(c, "axpby", [&] { return launch_axpby(rhs, -1.0, R, 0.0, nullptr, N, c->stream); });
         s != FEOD_OK)
