@@ -173,6 +173,11 @@ def test_element_tangents_match_oracle(w):
     # a sub-range of elements gives the same matrices
     part = host(prob.element_tangents(dev(inp["u"]), first=1, count=ora.E - 2))
     assert np.array_equal(part, Ke[1:-1])
+    # counts that leave a workgroup's element batch partly empty
+    for cnt in (1, 3, 5):
+        if 2 + cnt <= ora.E:
+            part = host(prob.element_tangents(dev(inp["u"]), first=2, count=cnt))
+            assert np.array_equal(part, Ke[2:2 + cnt])
 
 
 def test_element_tangents_sampled_on_design_mesh():
