@@ -35,7 +35,7 @@ inline FastDiv make_fastdiv(uint32_t d) {
   const uint64_t p = uint64_t(1) << (31 + l);
   return {(uint32_t)((p + d - 1) / d), 31 + l};
 }
-__device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
+__host__ __device__ __forceinline__ uint32_t fastdiv(uint32_t n, FastDiv f) {
   return (uint32_t)(((uint64_t)n * f.m) >> f.s);
 }
 
