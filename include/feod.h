@@ -184,8 +184,9 @@ feod_status feod_element_tangents(feod_ctx* ctx, const double* u, int64_t first,
                                   double* Ke);
 
 /* Partial assembly (the pointwise data of Fig. 1's caption): store the
- * reference gradients of M u at every quadrature point (3 per point, in the
- * precision of prec) in the workspace, so that feod_jacobian_apply_pa can
+ * gradients of M u at every quadrature point (3 per point, in the precision
+ * of prec; physical gradients on affine meshes, reference ones on curved
+ * meshes) in the workspace, so that feod_jacobian_apply_pa can
  * apply J(u) without recomputing the gradient of u. */
 feod_status feod_pa_setup(feod_ctx* ctx, const double* u, feod_prec prec);
 

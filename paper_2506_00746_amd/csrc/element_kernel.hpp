@@ -29,12 +29,20 @@
 
 namespace feod {
 
-// 1D tables by value in the kernel arguments: B[q*D1+a] = l_a(x_q),
-// D[q*D1+a] = l_a'(x_q), Gauss weights w and points xi on [0,1].
+// 1D tables by value in the kernel arguments: B[q*D1+a] = l_a(x_q), the
+// derivative table of each direction Dx, Dy, Dz[q*D1+a] = l_a'(x_q) / h_dir,
+// Gauss weights w and points xi on [0,1].  On affine meshes the 1/h factor of
+// each direction rides in its derivative table, so the passes produce
+// physical gradients and take back physical fluxes with no per-point scaling;
+// on curved meshes (and for the tangent kernel) the three are the reference
+// table l_a'(x_q).  Each phase contracts along one direction and reads only
+// that direction's table.
 template <int D1, int NQ, class T>
 struct Tab {
   T B[NQ * D1];
-  T D[NQ * D1];
+  T Dx[NQ * D1];
+  T Dy[NQ * D1];
+  T Dz[NQ * D1];
   T w[NQ];
   T xi[NQ];
 };
@@ -163,11 +171,11 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
       T* x = Xs + el * XSTRIDE + f * 2 * XS + c * NQ * XQ + b;
 #pragma unroll(Unroll<NQ>::full ? NQ : 1)
       for (int qx = 0; qx < NQ; ++qx) {
-        T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.D[qx * D1] * in[f][0];
+        T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.Dx[qx * D1] * in[f][0];
 #pragma unroll
         for (int a = 1; a < D1; ++a) {
           s0 += tb.B[qx * D1 + a] * in[f][a];
-          s1 += tb.D[qx * D1 + a] * in[f][a];
+          s1 += tb.Dx[qx * D1 + a] * in[f][a];
         }
         x[qx * XQ] = s0;
         x[XS + qx * XQ] = s1;
@@ -201,7 +209,7 @@ __device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const 
     for (int qz = 0; qz < NQ; ++qz) {
       gf[0][qz] += tb.B[qz * D1 + c] * y2;
       gf[1][qz] += tb.B[qz * D1 + c] * y0;
-      gf[2][qz] += tb.D[qz * D1 + c] * y1;
+      gf[2][qz] += tb.Dz[qz * D1 + c] * y1;
     }
   }
 }
@@ -231,6 +239,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
   constexpr int VTX = CURVED ? 24 : 0;  // vertex coordinates per element (curved meshes only)
   __shared__ T smem[EB * (L::region + VTX)];
   __shared__ T sB[NQ * L::XQ], sD[NQ * L::XQ];  // table rows, same padded stride
+  __shared__ T sW[NQ], sXi[NQ];                  // weights and points, read with per-thread indices
   T* Xs = smem;                     // [el][f][s][c][qx][b], later K [el][o][s][c][qx][b]
   T* Hs = smem + EB * L::HOFF;      // [el][o][d][c][qy][qx]; per-line sums for reductions
   T* Vs = smem + EB * L::region;    // [el][24] vertex coordinates
@@ -249,7 +258,11 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
   for (int i = tid; i < NQ * D1; i += NT) {
     const int q = i / D1, a = i - q * D1;
     sB[q * L::XQ + a] = tb.B[i];
-    sD[q * L::XQ + a] = tb.D[i];
+    sD[q * L::XQ + a] = tb.Dy[i];
+  }
+  for (int i = tid; i < NQ; i += NT) {
+    sW[i] = tb.w[i];
+    sXi[i] = tb.xi[i];
   }
   if (CURVED) {
     for (int i = tid; i < EB * 24; i += NT) {
@@ -341,12 +354,12 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
   if (active && !QSTORE) {
     const bool valid = el < n_valid;
     const T rho = (P.rho != nullptr && valid) ? (T)P.rho[e0 + el] : T(1);
-    const T wxy = tb.w[qx] * tb.w[qy];
+    const T wxy = sW[qx] * sW[qy];
     // geometry: affine -> constant diagonal; curved -> Jg = J0 + xi_z J1 (column 2 constant)
     T J0[3][3], J1[3][2];
     if (CURVED) {
       const T* X = Vs + el * 24;
-      const T xi = tb.xi[qx], et = tb.xi[qy], mx = T(1) - xi, me = T(1) - et;
+      const T xi = sXi[qx], et = sXi[qy], mx = T(1) - xi, me = T(1) - et;
 #pragma unroll
       for (int al = 0; al < 3; ++al) {
         const T* x = X + al;  // x[3v] = coordinate al of vertex v = i + 2j + 4l
@@ -397,11 +410,11 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
             gv[a] = (adj[0][a] * g[1][0][qz] + adj[1][a] * g[1][1][qz] + adj[2][a] * g[1][2][qz]) * inv_det;
         }
       } else {
-        det = (T)P.det;
+        det = (T)P.det;  // the derivative tables carry 1/h: g is already physical
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          gu[a] = g[0][a][qz] * (T)P.hinv[a];
-          if constexpr (F == 2) gv[a] = g[1][a][qz] * (T)P.hinv[a];
+          gu[a] = g[0][a][qz];
+          if constexpr (F == 2) gv[a] = g[1][a][qz];
         }
       }
       T Fo[O][3];
@@ -435,7 +448,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
 #pragma unroll
           for (int i = 0; i < 3; ++i)
 #pragma unroll
-            for (int j = 0; j < 3; ++j) Ch[i][j] = s * det * (T)P.hinv[i] * (T)P.hinv[j] * Tm[i][j];
+            for (int j = 0; j < 3; ++j) Ch[i][j] = (s * det) * Tm[i][j];  // 1/h in the tables
         }
         cd[0][qz] = Ch[0][0];
         cd[1][qz] = Ch[1][1];
@@ -465,8 +478,10 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
         part -= (double)(w3 * det * cf * (gu[0] * gv[0] + gu[1] * gv[1] + gu[2] * gv[2]));
       }
       if constexpr (!REDUCE && !DIAG) {
-        // reference flux Fhat = rho w det Jg^{-1} F = rho w adj F (stored over g)
+        // reference flux Fhat = rho w det Jg^{-1} F = rho w adj F (stored over g);
+        // affine: rho w det F, the 1/h of Jg^{-1} being in the tables
         const T s = rho * w3;
+        const T sd = s * det;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
 #pragma unroll
@@ -474,7 +489,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
             if (CURVED)
               g[o][a][qz] = s * (adj[a][0] * Fo[o][0] + adj[a][1] * Fo[o][1] + adj[a][2] * Fo[o][2]);
             else
-              g[o][a][qz] = s * (T)P.sdet[a] * Fo[o][a];
+              g[o][a][qz] = sd * Fo[o][a];
           }
         }
       }
@@ -489,7 +504,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
         T s[6] = {0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int qz = 0; qz < NQ; ++qz) {
-          const T bz = tb.B[qz * D1 + c], dz = tb.D[qz * D1 + c];
+          const T bz = tb.B[qz * D1 + c], dz = tb.Dz[qz * D1 + c];
           const T bb = bz * bz, dd = dz * dz, bd = bz * dz;
           s[0] += bb * cd[0][qz];
           s[1] += bb * cd[1][qz];
@@ -508,12 +523,12 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
         T* h = Hs + el * L::HSTR + o * 3 * D1 * NQ2 + qxy;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
         for (int c = 0; c < D1; ++c) {
-          T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.D[c] * g[o][2][0];
+          T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.Dz[c] * g[o][2][0];
 #pragma unroll
           for (int qz = 1; qz < NQ; ++qz) {
             s0 += tb.B[qz * D1 + c] * g[o][0][qz];
             s1 += tb.B[qz * D1 + c] * g[o][1][qz];
-            s2 += tb.D[qz * D1 + c] * g[o][2][qz];
+            s2 += tb.Dz[qz * D1 + c] * g[o][2][qz];
           }
           h[c * NQ2] = s0;
           h[D1 * NQ2 + c * NQ2] = s1;
@@ -560,7 +575,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
           T kd2 = 0, kb2 = 0, kdb = 0;
 #pragma unroll
           for (int qy = 0; qy < NQ; ++qy) {
-            const T by = tb.B[qy * D1 + b], dy = tb.D[qy * D1 + b];
+            const T by = tb.B[qy * D1 + b], dy = tb.Dy[qy * D1 + b];
             const T bb = by * by, dd = dy * dy, bd = by * dy;
             kd2 += bb * hv[0][qy];
             kb2 += dd * hv[1][qy];
@@ -582,12 +597,12 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
           T* k = Xs + el * L::XSTR + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
           for (int b = 0; b < D1; ++b) {
-            T s0 = tb.B[b] * h0[0], s1 = tb.D[b] * h1[0];
+            T s0 = tb.B[b] * h0[0], s1 = tb.Dy[b] * h1[0];
             s1 += tb.B[b] * h2[0];
 #pragma unroll
             for (int qy = 1; qy < NQ; ++qy) {
               s0 += tb.B[qy * D1 + b] * h0[qy];
-              s1 += tb.D[qy * D1 + b] * h1[qy];
+              s1 += tb.Dy[qy * D1 + b] * h1[qy];
               s1 += tb.B[qy * D1 + b] * h2[qy];
             }
             k[b] = s0;
@@ -628,7 +643,7 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
         T sacc = 0;
 #pragma unroll
         for (int qx = 0; qx < NQ; ++qx) {
-          const T bx = tb.B[qx * D1 + a], dx = tb.D[qx * D1 + a];
+          const T bx = tb.B[qx * D1 + a], dx = tb.Dx[qx * D1 + a];
           sacc += dx * dx * kd2[qx];
           sacc += bx * bx * kb2[qx];
           sacc += bx * dx * kdb[qx];
@@ -650,11 +665,11 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
       T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) + pos;
 #pragma unroll(Unroll<D1>::full ? D1 : 1)
       for (int a = 0; a < D1; ++a) {
-        T s = tb.D[a] * k0[0];
+        T s = tb.Dx[a] * k0[0];
         s += tb.B[a] * k1[0];
 #pragma unroll
         for (int qx = 1; qx < NQ; ++qx) {
-          s += tb.D[qx * D1 + a] * k0[qx];
+          s += tb.Dx[qx * D1 + a] * k0[qx];
           s += tb.B[qx * D1 + a] * k1[qx];
         }
         out[a] = s;
@@ -663,12 +678,17 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
   }
 }
 
+// hs: the 1/h factor of each direction folded into its derivative table
+// (affine meshes), or nullptr for the reference tables.
 template <int D1, int NQ, class T>
-Tab<D1, NQ, T> make_tab(const double* h) {
+Tab<D1, NQ, T> make_tab(const double* h, const double* hs = nullptr) {
   Tab<D1, NQ, T> t;
   for (int i = 0; i < NQ * D1; ++i) {
+    const double d = h[NQ * D1 + i];
     t.B[i] = (T)h[i];
-    t.D[i] = (T)h[NQ * D1 + i];
+    t.Dx[i] = (T)(hs ? d * hs[0] : d);
+    t.Dy[i] = (T)(hs ? d * hs[1] : d);
+    t.Dz[i] = (T)(hs ? d * hs[2] : d);
   }
   for (int i = 0; i < NQ; ++i) {
     t.w[i] = (T)h[2 * NQ * D1 + i];
@@ -688,7 +708,7 @@ inline void no_tangents(ElemLaunchers&) {}
     constexpr int NT = Config<DD, QQ, T>::NT;                                                     \
     const int blocks = (P.E + EB - 1) / EB;                                                       \
     if (blocks == 0) return hipSuccess;                                                           \
-    const Tab<DD, QQ, T> tb = make_tab<DD, QQ, T>(P.htab);                                        \
+    const Tab<DD, QQ, T> tb = make_tab<DD, QQ, T>(P.htab, CURVED ? nullptr : P.hinv);             \
     hipLaunchKernelGGL((element_kernel<DD, QQ, T, OP, CURVED, PK>), dim3(blocks), dim3(NT), 0, s, \
                        P, tb);                                                                    \
     return hipGetLastError();                                                                     \

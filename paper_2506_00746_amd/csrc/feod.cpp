@@ -231,7 +231,6 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
   P.hinv[1] = c->ny;
   P.hinv[2] = c->nz;
   P.det = 1.0 / ((double)c->nx * c->ny * c->nz);
-  for (int a = 0; a < 3; ++a) P.sdet[a] = P.det * P.hinv[a];
   const double p = p_override > 0 ? p_override : c->p;
   P.p = p;
   P.eps2 = c->eps * c->eps;
@@ -979,24 +978,29 @@ feod_status feod_profile_read(feod_ctx* c, feod_kernel_stat* stats, int32_t max,
 // counted from the kernel source (FMA = 2, mul/add = 1, reciprocal square
 // root / division / pow = 1 each; a refined reciprocal square root is 1 + 8).
 static double pointwise_flops(int op, int pk, bool curved) {
+  // counted from the kernel source, FMA = 2, mul / add = 1, per point.
   // a^r: scalar and dual (value + tangent), by exponent kind
   const double apow_s[5] = {0, 20, 10, 0, 3};
   const double apow_d[5] = {0, 24, 12, 0, 6};
+  // common to both geometries: weight w3 and s = rho w3 (2), a = eps^2 + |g|^2
+  // (6 as a value, 17 as a dual), F = a^r g (3 as a value, 9 for the tangent)
   double f = 0;
   switch (op) {
-    case OP_RESIDUAL: f = 20 + apow_s[pk]; break;  // w, g, a, F, pull-back
-    case OP_JVP: f = 38 + apow_d[pk]; break;       // dual a and F, tangent pull-back
-    case OP_RESJVP: f = 44 + apow_d[pk]; break;    // + value pull-back
-    case OP_ENERGY: f = 16 + apow_s[pk]; break;    // a, W = a a^r / p, weight
-    case OP_GRAD: f = 22 + apow_s[pk]; break;      // a^r g_u . g_lambda, weight
-    case OP_JVP_PA: f = 38 + apow_d[pk]; break;    // as the Jacobian action
+    case OP_RESIDUAL: f = 2 + 6 + 3 + apow_s[pk]; break;
+    case OP_JVP: f = 2 + 17 + 9 + apow_d[pk]; break;
+    case OP_RESJVP: f = 2 + 17 + 12 + apow_d[pk]; break;  // tangent and value of F
+    case OP_ENERGY: f = 1 + 6 + 2 + 4 + apow_s[pk]; break;  // W = a a^r / p, accumulate rho w det W
+    case OP_GRAD: f = 1 + 6 + 5 + 4 + apow_s[pk]; break;    // a^r g_u . g_lambda, accumulate
+    case OP_JVP_PA: f = 2 + 17 + 9 + apow_d[pk]; break;
     default: f = 0;
   }
-  if (curved) {  // Jacobian, adjugate, determinant, transforms (per-line set-up amortised)
-    const double geo[OP_COUNT] = {78, 93, 105, 66, 81, 0, 0, 93};
-    f += geo[op];
-  }
-  return f;
+  // affine: the derivative tables carry 1/h; per point only sd = s det and
+  // the output scaling sd F (per output field)
+  const double affine[OP_COUNT] = {4, 4, 7, 0, 0, 0, 0, 4};
+  // curved: Jg (12), adjugate (27), det (5), 1/det (1), physical gradient per
+  // input field (18 each), reference flux s adj F per output field (18 each)
+  const double geo[OP_COUNT] = {81, 99, 117, 63, 81, 0, 0, 99};
+  return f + (curved ? geo[op] : affine[op]);
 }
 
 feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, double* bytes, double* flops) {

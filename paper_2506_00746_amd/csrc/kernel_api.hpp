@@ -49,14 +49,14 @@ struct ElemParams {
   const void* tab;        // 1D tables in the kernel precision: B, D (nq x D1), w, xi (nq)
   void* out0;             // E-vector (kernel precision) or E doubles (energy, gradient)
   void* out1;             // second E-vector (residual + JVP)
-  void* qdata;            // partial assembly: [e][d][qz][qy][qx] reference gradients (kernel precision)
+  void* qdata;            // partial assembly: [e][d][qz][qy][qx] gradients of u (kernel precision;
+                          // physical on affine meshes, reference on curved ones)
   const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
   int32_t e_first;        // first element (element-tangent kernel; E is then the count)
   int32_t k, Lx, Ly, Lz;  // order and node-lattice extents (k n + 1 per direction)
   double hinv[3];         // affine meshes: 1/h per direction
   double det;             // affine meshes: element volume h_x h_y h_z
-  double sdet[3];         // affine meshes: det * hinv
   double p, eps2, r, inv_p;
   int32_t powkind;
   FastDiv div_nx, div_ny;  // element index -> (ex, ey, ez)

@@ -35,7 +35,7 @@ __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, 
   const int tid = threadIdx.x;
   for (int i = tid; i < NQ * D1; i += NT) {
     sB[i] = tb.B[i];
-    sD[i] = tb.D[i];
+    sD[i] = tb.Dx[i];  // reference table (built without 1/h)
   }
   for (int i = tid; i < NQ; i += NT) {
     sW[i] = tb.w[i];
