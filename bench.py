@@ -188,11 +188,12 @@ def tangent_flops_per_element(k, nq):
     """Algorithmic FLOPs of one element tangent matrix (Eq. 3) as the kernel
     computes it: dense reference gradients (12 nq^3 (k+1)^3), the pointwise
     tangent by three dual evaluations plus transform (~150 per point), and the
-    sum-factorised B^T Chat B over 9 tensor terms, 3 FLOP per multiply-add
-    with a product table: 27 (nq^3 D1^2 + nq^2 D1^4 + nq D1^6)."""
+    sum-factorised B^T Chat B, 3 FLOP per term of each stage (two factors and
+    the accumulate): x and y stages for the 9 tensor terms, 27 (nq^3 D1^2 +
+    nq^2 D1^4), and the z stage once per z-factor pair, 12 nq D1^6."""
     d1 = k + 1
     return (12 * nq ** 3 * d1 ** 3 + 150 * nq ** 3
-            + 27 * (nq ** 3 * d1 ** 2 + nq ** 2 * d1 ** 4 + nq * d1 ** 6))
+            + 27 * (nq ** 3 * d1 ** 2 + nq ** 2 * d1 ** 4) + 12 * nq * d1 ** 6)
 
 
 def tangent_rows(feod, WORKLOADS, make_inputs, dev, args):

@@ -9,7 +9,8 @@
 // direction d, K[i][j] = sum_q sum_{d,d'} psi_d(q,i) Chat_dd'(q) psi_d'(q,j).
 // Each psi is a product of 1D factors, so every (d,d') term is contracted by
 // sum factorisation in three stages (x, then y, then z) through LDS:
-// O(nq^3 D1^2 + nq^2 D1^4 + nq D1^6) per term instead of the dense
+// O(nq^3 D1^2 + nq^2 D1^4) per term for the x and y stages, and the z stage
+// O(nq D1^6) once per z-factor pair (four, not nine), instead of the dense
 // O(nq^3 D1^6).  Supported for D1 <= 5 (the y-stage buffer nq D1^4 must fit).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -135,44 +136,53 @@ __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, 
   T acc[PER];
 #pragma unroll
   for (int m = 0; m < PER; ++m) acc[m] = 0;
-  for (int d = 0; d < 3; ++d) {
-    for (int d2 = 0; d2 < 3; ++d2) {
-      const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
-      const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
-      const T* Fy0 = d == 1 ? sD : sB;
-      const T* Fy1 = d2 == 1 ? sD : sB;
-      const T* Fz0 = d == 2 ? sD : sB;
-      const T* Fz1 = d2 == 2 ? sD : sB;
-      const T* Cdd = sC[d * 3 + d2];
-      // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
-      for (int i = tid; i < NQ * NQ * D2; i += NT) {
-        const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
-        T sacc = 0;
-        for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
-        sT1[i] = sacc;
-      }
-      __syncthreads();
-      // y: T2[qz][b][b'][a][a'] = sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
-      for (int i = tid; i < NQ * D4; i += NT) {
-        const int aa = i % D2, bb = (i / D2) % D2, qz = i / D4, b = bb / D1, b2 = bb % D1;
-        T sacc = 0;
-        for (int qy = 0; qy < NQ; ++qy) sacc += Fy0[qy * D1 + b] * Fy1[qy * D1 + b2] * sT1[(qz * NQ + qy) * D2 + aa];
-        sT2[i] = sacc;
-      }
-      __syncthreads();
-      // z: K[c][c'][b][b'][a][a'] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][b][b'][a][a']
-#pragma unroll
-      for (int m = 0; m < PER; ++m) {
-        const int L = tid + m * NT;
-        if (L < NE2) {
-          const int ab = L % D4, cc = L / D4, c = cc / D1, c2 = cc % D1;
+  // The z factor of psi_d is D for d = 2 and B otherwise, so the nine (d,d')
+  // terms fall into four groups by their z-factor pair; the z stage is linear,
+  // so each group's y-stage outputs are summed first and contracted in z once.
+  for (int zg = 0; zg < 4; ++zg) {
+    const bool zd0 = zg & 1, zd1 = zg >> 1;  // z factor of psi_d / psi_d' is D
+    for (int i = tid; i < NQ * D4; i += NT) sT2[i] = 0;
+    for (int d = 0; d < 3; ++d) {
+      if ((d == 2) != zd0) continue;
+      for (int d2 = 0; d2 < 3; ++d2) {
+        if ((d2 == 2) != zd1) continue;
+        const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
+        const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
+        const T* Fy0 = d == 1 ? sD : sB;
+        const T* Fy1 = d2 == 1 ? sD : sB;
+        const T* Cdd = sC[d * 3 + d2];
+        // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
+        for (int i = tid; i < NQ * NQ * D2; i += NT) {
+          const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
           T sacc = 0;
-          for (int qz = 0; qz < NQ; ++qz) sacc += Fz0[qz * D1 + c] * Fz1[qz * D1 + c2] * sT2[qz * D4 + ab];
-          acc[m] += sacc;
+          for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
+          sT1[i] = sacc;
         }
+        __syncthreads();
+        // y: T2[qz][b][b'][a][a'] += sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
+        for (int i = tid; i < NQ * D4; i += NT) {
+          const int aa = i % D2, bb = (i / D2) % D2, qz = i / D4, b = bb / D1, b2 = bb % D1;
+          T sacc = 0;
+          for (int qy = 0; qy < NQ; ++qy) sacc += Fy0[qy * D1 + b] * Fy1[qy * D1 + b2] * sT1[(qz * NQ + qy) * D2 + aa];
+          sT2[i] += sacc;
+        }
+        __syncthreads();
       }
-      __syncthreads();
     }
+    // z: K[c][c'][b][b'][a][a'] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][b][b'][a][a']
+    const T* Fz0 = zd0 ? sD : sB;
+    const T* Fz1 = zd1 ? sD : sB;
+#pragma unroll
+    for (int m = 0; m < PER; ++m) {
+      const int L = tid + m * NT;
+      if (L < NE2) {
+        const int ab = L % D4, cc = L / D4, c = cc / D1, c2 = cc % D1;
+        T sacc = 0;
+        for (int qz = 0; qz < NQ; ++qz) sacc += Fz0[qz * D1 + c] * Fz1[qz * D1 + c2] * sT2[qz * D4 + ab];
+        acc[m] += sacc;
+      }
+    }
+    __syncthreads();
   }
   // K_e row i = a + D1 (b + D1 c), column j = a' + D1 (b' + D1 c'), row-major
   T* Ke = static_cast<T*>(P.out0) + (int64_t)blockIdx.x * NE2;
