@@ -186,12 +186,20 @@ def solve_rows(feod, WORKLOADS, make_inputs, dev):
 
 def tangent_flops_per_element(k, nq):
     """Algorithmic FLOPs of one element tangent matrix (Eq. 3) as the kernel
-    computes it: dense reference gradients (12 nq^3 (k+1)^3), the pointwise
+    computes it.  Sum-factorised kernel: dense reference gradients (12 nq^3 (k+1)^3), the pointwise
     tangent by three dual evaluations plus transform (~150 per point), and the
     sum-factorised B^T Chat B, 3 FLOP per term of each stage (two factors and
     the accumulate): x and y stages for the 9 tensor terms, 27 (nq^3 D1^2 +
     nq^2 D1^4), and the z stage once per z-factor pair, 12 nq D1^6."""
     d1 = k + 1
+    if d1 == 3:
+        # matrix-core path: K = G^T W with G the 3 nq^3 x 27 table of
+        # reference derivatives and W = Chat G (3 FMA per entry); the
+        # symmetric product is computed on 3 of the 4 16x16 tiles (553 of the
+        # 729 entries, the rest written by symmetry); plus the gradient of u
+        # at the points and Chat
+        kd, ne = 3 * nq ** 3, 27
+        return 2 * kd * ne + 150 * nq ** 3 + 6 * kd * ne + 2 * kd * (16 * 16 + 16 * 11 + 11 * 11)
     return (12 * nq ** 3 * d1 ** 3 + 150 * nq ** 3
             + 27 * (nq ** 3 * d1 ** 2 + nq ** 2 * d1 ** 4) + 12 * nq * d1 ** 6)
 
@@ -211,7 +219,8 @@ def tangent_rows(feod, WORKLOADS, make_inputs, dev, args):
         ms = timed_loop(lambda: pb.element_tangents(u, out=Ke), max(3, args.steps // 10), 2)
         flops = tangent_flops_per_element(w.k, w.nq) * w.n_elems
         bytes_ = Ke.numel() * 8 + 8 * w.n_dofs
-        out[name] = {"ms_per_launch": ms, "ns_per_element": ms * 1e6 / w.n_elems,
+        out[name] = {"path": "mfma" if w.k == 2 else "vector", "ms_per_launch": ms,
+                     "ns_per_element": ms * 1e6 / w.n_elems,
                      "TFLOP/s": flops / (ms * 1e-3) / 1e12, "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS,
                      "GB/s": bytes_ / (ms * 1e-3) / 1e9, "matrix_entries": Ke.numel()}
         log(f"[bench] element tangents {name}: {out[name]}")
