@@ -22,8 +22,10 @@ constexpr int kNumVec = 10;   // solver temporaries of length N
 constexpr int kScalars = 64;  // device scalar slots
 enum Vec { V_R = 0, V_DU, V_CR, V_CP, V_CQ, V_CZ, V_DINV, V_UT, V_AUX, V_AUX2 };
 enum Scal { S_RZ = 0, S_PQ = 2, S_RR = 3, S_A = 4, S_B = 5, S_E = 6, S_T = 7 };
-// CG partial-sum slots, kCgBlocks doubles each: p.q, r.z (two, alternating), r.r
+// CG partial-sum slots of kCgSlot doubles: p.q (up to kGatherDotMaxBlocks
+// partials from the gather), r.z (two, alternating) and r.r (kCgBlocks each)
 enum CgPart { C_PQ = 0, C_RZ0, C_RZ1, C_RR, kCgParts };
+constexpr int kCgSlot = kGatherDotMaxBlocks > kCgBlocks ? kGatherDotMaxBlocks : kCgBlocks;
 
 thread_local std::string g_setup_error;
 
@@ -60,7 +62,7 @@ struct feod_ctx {
   int pa_prec = -1;  // precision of the stored partial-assembly data, -1: none
   double* d_vec[kNumVec] = {};
   double *d_part0 = nullptr, *d_part1 = nullptr, *d_cgpart = nullptr, *d_sc = nullptr;
-  double* cg_part(int slot) const { return d_cgpart + (size_t)slot * kCgBlocks; }
+  double* cg_part(int slot) const { return d_cgpart + (size_t)slot * kCgSlot; }
   // profiling
   bool prof = false;
   std::vector<hipEvent_t> events;
@@ -132,7 +134,7 @@ Layout layout(const feod_ctx* c) {
   l.vec = take(kNumVec * align_up(N * 8));
   l.part0 = take(kRedBlocks * 8);
   l.part1 = take(kRedBlocks * 8);
-  l.cgpart = take(kCgParts * kCgBlocks * 8);
+  l.cgpart = take(kCgParts * kCgSlot * 8);
   l.sc = take(kScalars * 8);
   l.total = off;
   return l;
@@ -415,7 +417,8 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
       TRY(run_element(c, OP_JVP, prec, params(c, u, p, c->d_Y0, nullptr, prec, p_override)));
     TRY(gather_t_dot(c, prec == 1, p, q));
     TRY(timed(c, "cg_step", [&] {
-      return launch_cg_step(x, r, z, p, q, dinv, c->cg_part(cur), c->cg_part(C_PQ), N, c->cg_part(nxt),
+      return launch_cg_step(x, r, z, p, q, dinv, c->cg_part(cur), c->cg_part(C_PQ), gather_dot_blocks(N), N,
+                            c->cg_part(nxt),
                             c->cg_part(C_RR), c->d_sc, S_RZ, S_PQ, c->stream);
     }));
     out->iters = it + 1;

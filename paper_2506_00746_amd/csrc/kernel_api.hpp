@@ -128,7 +128,14 @@ constexpr int kCgBlocks = 512;   // partial sums per CG inner product (two block
 constexpr int kCgThreads = 512;  // threads per CG vector block
 constexpr int kCgUnroll = 4;     // DOFs per thread per grid-stride pass
 // q = G^T Y (lattice map when d != null, else the CSR map off/idx) and
-// partial[b] = block b's share of p.q.
+// partial[b] = block b's share of p.q, for gather_dot_blocks(n) blocks of
+// kGatherDotThreads (one DOF per thread up to kGatherDotMaxBlocks blocks).
+constexpr int kGatherDotThreads = 1024;
+constexpr int kGatherDotMaxBlocks = 4096;
+inline int gather_dot_blocks(int64_t n) {
+  const int64_t b = (n + kGatherDotThreads - 1) / kGatherDotThreads;
+  return (int)(b < 1 ? 1 : (b > kGatherDotMaxBlocks ? kGatherDotMaxBlocks : b));
+}
 hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
                                bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s);
 // x = 0, r = b, z = dinv r (z may alias r when dinv is null), p = z, partials of r.z and r.r
@@ -138,11 +145,12 @@ hipError_t launch_cg_init(double* x, double* r, double* z, double* p, const doub
 // partials of r.z and r.r; x and p are left as they are.
 hipError_t launch_cg_true_residual(double* r, double* z, const double* b, const double* jx, const double* dinv,
                                    int64_t n, double* part_rz, double* part_rr, hipStream_t s);
-// alpha = sum(part_rz)/sum(part_pq); x += alpha p; r -= alpha q; z = dinv r;
-// new partials of r.z (part_rz_new) and r.r (part_rr, when dinv); block 0
-// stores the two totals in sc[i_rz], sc[i_pq].
+// alpha = sum(part_rz)/sum(part_pq) (n_pq partials of p.q from the gather);
+// x += alpha p; r -= alpha q; z = dinv r; new partials of r.z (part_rz_new)
+// and r.r (part_rr, when dinv); block 0 stores the two totals in sc[i_rz],
+// sc[i_pq].
 hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
-                          const double* part_rz, const double* part_pq, int64_t n, double* part_rz_new,
+                          const double* part_rz, const double* part_pq, int n_pq, int64_t n, double* part_rz_new,
                           double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s);
 // beta = sum(part_new)/sum(part_old); p = z + beta p
 hipError_t launch_cg_direction(double* p, const double* z, const double* part_new, const double* part_old,

@@ -266,10 +266,24 @@ __device__ __forceinline__ double cg_block_sum(double v, double* ws) {
   return s;
 }
 
-__device__ __forceinline__ double cg_total(const double* __restrict__ part, double* ws) {
+__device__ __forceinline__ double cg_total(const double* __restrict__ part, double* ws, int count = kCgBlocks) {
   double v = 0;
-  for (int i = threadIdx.x; i < kCgBlocks; i += kCgThreads) v += part[i];
+  for (int i = threadIdx.x; i < count; i += kCgThreads) v += part[i];
   return cg_block_sum(v, ws);
+}
+
+// Block sum for the gather kernels (kGatherDotThreads threads), fixed order.
+__device__ __forceinline__ double gather_block_sum(double v) {
+  __shared__ double ws[kGatherDotThreads / 64];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) ws[w] = v;
+  __syncthreads();
+  double s = 0;
+#pragma unroll
+  for (int i = 0; i < kGatherDotThreads / 64; ++i) s += ws[i];
+  return s;  // the same in every thread
 }
 
 // The grid-stride kernels below take kCgUnroll DOFs per thread per pass (i,
@@ -277,59 +291,50 @@ __device__ __forceinline__ double cg_total(const double* __restrict__ part, doub
 // the end are clamped to n-1 for the loads and skipped for stores and sums.
 // Each thread still adds its DOFs in ascending order.
 
-// q = G^T Y and partial[b] = sum of p[i] q[i] over block b's share.
+// q = G^T Y and partial[b] = sum of p[i] q[i] over block b's share: one DOF
+// per thread (grid-stride only past kGatherDotMaxBlocks blocks), as in the
+// plain gather, so that the whole grid's loads are in flight at once.
 template <class TE>
-__global__ __launch_bounds__(kCgThreads) void gather_t_lattice_dot_kernel(LatticeDims d, const TE* __restrict__ Y,
-                                                                          const double* __restrict__ p,
-                                                                          double* __restrict__ q, int64_t n,
-                                                                          double* __restrict__ partial) {
-  __shared__ double ws[kCgThreads / 64];
+__global__ __launch_bounds__(kGatherDotThreads) void gather_t_lattice_dot_kernel(LatticeDims d,
+                                                                                 const TE* __restrict__ Y,
+                                                                                 const double* __restrict__ p,
+                                                                                 double* __restrict__ q, int64_t n,
+                                                                                 double* __restrict__ partial) {
   double acc = 0;
-  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
-  for (int64_t i0 = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i0 < n; i0 += kCgUnroll * stride) {
-    double s[kCgUnroll], pv[kCgUnroll], unused;
-#pragma unroll
-    for (int u = 0; u < kCgUnroll; ++u) {
-      const int64_t i = min(i0 + u * stride, n - 1);
-      lattice_row_sum<TE, false>(d, Y, nullptr, i, s[u], unused);
-      pv[u] = p[i];
-    }
-#pragma unroll
-    for (int u = 0; u < kCgUnroll; ++u) {
-      const int64_t i = i0 + u * stride;
-      if (i < n) {
-        q[i] = s[u];
-        acc += pv[u] * s[u];
-      }
-    }
+  const int64_t stride = (int64_t)gridDim.x * kGatherDotThreads;
+  for (int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kGatherDotThreads + threadIdx.x; i < n;
+       i += stride) {
+    double s0, s1;
+    lattice_row_sum<TE, false>(d, Y, nullptr, i, s0, s1);
+    q[i] = s0;
+    acc += p[i] * s0;
   }
-  acc = cg_block_sum(acc, ws);
+  acc = gather_block_sum(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 template <class TE>
-__global__ __launch_bounds__(kCgThreads) void gather_t_dot_kernel(const int32_t* __restrict__ off,
-                                                                  const int32_t* __restrict__ idx,
-                                                                  const TE* __restrict__ Y,
-                                                                  const double* __restrict__ p,
-                                                                  double* __restrict__ q, int64_t n,
-                                                                  double* __restrict__ partial) {
-  __shared__ double ws[kCgThreads / 64];
+__global__ __launch_bounds__(kGatherDotThreads) void gather_t_dot_kernel(const int32_t* __restrict__ off,
+                                                                         const int32_t* __restrict__ idx,
+                                                                         const TE* __restrict__ Y,
+                                                                         const double* __restrict__ p,
+                                                                         double* __restrict__ q, int64_t n,
+                                                                         double* __restrict__ partial) {
   double acc = 0;
-  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += stride) {
+  const int64_t stride = (int64_t)gridDim.x * kGatherDotThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kGatherDotThreads + threadIdx.x; i < n; i += stride) {
     double s = 0;
     for (int j = off[i]; j < off[i + 1]; ++j) s += (double)Y[idx[j]];
     q[i] = s;
     acc += p[i] * s;
   }
-  acc = cg_block_sum(acc, ws);
+  acc = gather_block_sum(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
 hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
                                bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s) {
-  const dim3 g(kCgBlocks), b(kCgThreads);
+  const dim3 g(gather_dot_blocks(n)), b(kGatherDotThreads);
   if (d) {
     if (fp32)
       hipLaunchKernelGGL((gather_t_lattice_dot_kernel<float>), g, b, 0, s, *d, (const float*)Y, p, q, n, partial);
@@ -436,7 +441,7 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
                                                              const double* __restrict__ q,
                                                              const double* __restrict__ dinv,
                                                              const double* __restrict__ part_rz,
-                                                             const double* __restrict__ part_pq, int64_t n,
+                                                             const double* __restrict__ part_pq, int n_pq, int64_t n,
                                                              double* __restrict__ part_rz_new,
                                                              double* __restrict__ part_rr, double* __restrict__ sc,
                                                              int i_rz, int i_pq) {
@@ -457,7 +462,7 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
     }
   };
   if (first < n) load(first);
-  const double rz = cg_total(part_rz, ws), pq = cg_total(part_pq, ws);
+  const double rz = cg_total(part_rz, ws), pq = cg_total(part_pq, ws, n_pq);
   const double alpha = rz / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[i_rz] = rz;
@@ -493,14 +498,14 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
 }
 
 hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
-                          const double* part_rz, const double* part_pq, int64_t n, double* part_rz_new,
+                          const double* part_rz, const double* part_pq, int n_pq, int64_t n, double* part_rz_new,
                           double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s) {
   if (dinv)
     hipLaunchKernelGGL(cg_step_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, z, p, q, dinv, part_rz,
-                       part_pq, n, part_rz_new, part_rr, sc, i_rz, i_pq);
+                       part_pq, n_pq, n, part_rz_new, part_rr, sc, i_rz, i_pq);
   else
     hipLaunchKernelGGL(cg_step_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, r, p, q, nullptr,
-                       part_rz, part_pq, n, part_rz_new, nullptr, sc, i_rz, i_pq);
+                       part_rz, part_pq, n_pq, n, part_rz_new, nullptr, sc, i_rz, i_pq);
   return hipGetLastError();
 }
 
