@@ -37,15 +37,129 @@ namespace feod {
 // on curved meshes (and for the tangent kernel) the three are the reference
 // table l_a'(x_q).  Each phase contracts along one direction and reads only
 // that direction's table.
+// Even-odd form of a 1D table.  The Gauss-Lobatto nodes and the Gauss points
+// are symmetric about 1/2, so the value table is symmetric under the
+// reflection (q, a) -> (NQ-1-q, D1-1-a) and a derivative table antisymmetric.
+// Splitting a contraction's input into even and odd parts under the
+// reflection roughly halves its multiply-adds.  Stored for the first
+// QP = ceil(NQ/2) rows: P[q][a] = (M[q][a] + M[q][D1-1-a]) / 2 and
+// N[q][a] = (M[q][a] - M[q][D1-1-a]) / 2 for a < D1/2, and the middle
+// column P[q][D1/2] = M[q][D1/2] when D1 is odd.
+template <int D1, int NQ>
+struct EO {
+  static constexpr int AH = D1 / 2, AP = (D1 + 1) / 2, QH = NQ / 2, QP = (NQ + 1) / 2;
+};
+
 template <int D1, int NQ, class T>
 struct Tab {
+  using E = EO<D1, NQ>;
   T B[NQ * D1];
   T Dx[NQ * D1];
   T Dy[NQ * D1];
   T Dz[NQ * D1];
   T w[NQ];
   T xi[NQ];
+  // even-odd forms of B, Dx, Dy, Dz (the contractions of phases A, C, D, E)
+  T Pb[E::QP * E::AP], Nb[E::QP * E::AH];
+  T Px[E::QP * E::AP], Nx[E::QP * E::AH];
+  T Py[E::QP * E::AP], Ny[E::QP * E::AH];
+  T Pz[E::QP * E::AP], Nz[E::QP * E::AH];
 };
+
+// Even and odd parts of a line of D1 values (e[AH] = middle value, D1 odd).
+template <int D1, int NQ, class T>
+__device__ __forceinline__ void eo_split(const T (&x)[D1], T (&e)[EO<D1, NQ>::AP], T (&o)[EO<D1, NQ>::AH]) {
+  constexpr int AH = EO<D1, NQ>::AH;
+#pragma unroll
+  for (int a = 0; a < AH; ++a) {
+    e[a] = x[a] + x[D1 - 1 - a];
+    o[a] = x[a] - x[D1 - 1 - a];
+  }
+  if constexpr (D1 % 2) e[AH] = x[AH];
+}
+
+// y = M x (D1 values -> NQ points) from the even / odd parts of x; SYM: M is
+// a value table (symmetric), else a derivative table (antisymmetric).
+template <int D1, int NQ, bool SYM, class T>
+__device__ __forceinline__ void eo_forward(const T* P, const T* N, const T (&e)[EO<D1, NQ>::AP],
+                                           const T (&o)[EO<D1, NQ>::AH], T (&y)[NQ]) {
+  using E = EO<D1, NQ>;
+#pragma unroll
+  for (int q = 0; q < E::QH; ++q) {
+    T s = P[q * E::AP] * e[0];
+#pragma unroll
+    for (int a = 1; a < E::AP; ++a) s += P[q * E::AP + a] * e[a];
+    T d = N[q * E::AH] * o[0];
+#pragma unroll
+    for (int a = 1; a < E::AH; ++a) d += N[q * E::AH + a] * o[a];
+    y[q] = s + d;
+    y[NQ - 1 - q] = SYM ? s - d : d - s;
+  }
+  if constexpr (NQ % 2) {
+    constexpr int q = E::QH;
+    if constexpr (SYM) {
+      T s = P[q * E::AP] * e[0];
+#pragma unroll
+      for (int a = 1; a < E::AP; ++a) s += P[q * E::AP + a] * e[a];
+      y[q] = s;
+    } else {
+      T d = N[q * E::AH] * o[0];
+#pragma unroll
+      for (int a = 1; a < E::AH; ++a) d += N[q * E::AH + a] * o[a];
+      y[q] = d;
+    }
+  }
+}
+
+// Backward (transposed) contraction y[a] = sum_q M[q][a] x[q] (NQ points ->
+// D1 values), accumulated in even-odd form: x is given by its pair sums
+// xe[q] = x[q] + x[NQ-1-q], differences xo[q] = x[q] - x[NQ-1-q] (q < NQ/2)
+// and middle value xm (NQ odd); the results add into sp (a < AP) and sm
+// (a < AH), from which eo_backward_finish forms y.  Several contractions
+// (different tables and inputs) can add into the same sp, sm.
+template <int D1, int NQ, bool SYM, class T>
+__device__ __forceinline__ void eo_backward_add(const T* P, const T* N, const T (&xe)[EO<D1, NQ>::QH + 1],
+                                                const T (&xo)[EO<D1, NQ>::QH + 1], T xm, T (&sp)[EO<D1, NQ>::AP],
+                                                T (&sm)[EO<D1, NQ>::AH]) {
+  using E = EO<D1, NQ>;
+#pragma unroll
+  for (int a = 0; a < E::AP; ++a) {
+#pragma unroll
+    for (int q = 0; q < E::QH; ++q) sp[a] += P[q * E::AP + a] * (SYM ? xe[q] : xo[q]);
+    if constexpr (SYM && NQ % 2) sp[a] += P[E::QH * E::AP + a] * xm;
+  }
+#pragma unroll
+  for (int a = 0; a < E::AH; ++a) {
+#pragma unroll
+    for (int q = 0; q < E::QH; ++q) sm[a] += N[q * E::AH + a] * (SYM ? xo[q] : xe[q]);
+    if constexpr (!SYM && NQ % 2) sm[a] += N[E::QH * E::AH + a] * xm;
+  }
+}
+
+template <int D1, int NQ, class T>
+__device__ __forceinline__ void eo_pairs(const T (&x)[NQ], T (&xe)[EO<D1, NQ>::QH + 1], T (&xo)[EO<D1, NQ>::QH + 1],
+                                         T& xm) {
+  constexpr int QH = EO<D1, NQ>::QH;
+#pragma unroll
+  for (int q = 0; q < QH; ++q) {
+    xe[q] = x[q] + x[NQ - 1 - q];
+    xo[q] = x[q] - x[NQ - 1 - q];
+  }
+  xe[QH] = xo[QH] = T(0);
+  xm = NQ % 2 ? x[QH] : T(0);
+}
+
+template <int D1, int NQ, class T>
+__device__ __forceinline__ void eo_backward_finish(const T (&sp)[EO<D1, NQ>::AP], const T (&sm)[EO<D1, NQ>::AH],
+                                                   T (&y)[D1]) {
+  constexpr int AH = EO<D1, NQ>::AH;
+#pragma unroll
+  for (int a = 0; a < AH; ++a) {
+    y[a] = sp[a] + sm[a];
+    y[D1 - 1 - a] = sp[a] - sm[a];
+  }
+  if constexpr (D1 % 2) y[AH] = sp[AH];
+}
 
 // Launch shape per (D1, NQ, precision): NT threads per workgroup and EB
 // elements per batch, so that phase C (NQ^2 lines per element, most of the
@@ -169,16 +283,29 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
       T* x = Xs + el * XSTRIDE + f * 2 * XS + c * NQ * XQ + b;
-#pragma unroll(Unroll<NQ>::full ? NQ : 1)
-      for (int qx = 0; qx < NQ; ++qx) {
-        T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.Dx[qx * D1] * in[f][0];
+      if constexpr (Unroll<D1>::full) {
+        // values (B) and x-derivatives (Dx) at the NQ points, even-odd form
+        T e[EO<D1, NQ>::AP], o[EO<D1, NQ>::AH], y0[NQ], y1[NQ];
+        eo_split<D1, NQ>(in[f], e, o);
+        eo_forward<D1, NQ, true>(tb.Pb, tb.Nb, e, o, y0);
+        eo_forward<D1, NQ, false>(tb.Px, tb.Nx, e, o, y1);
 #pragma unroll
-        for (int a = 1; a < D1; ++a) {
-          s0 += tb.B[qx * D1 + a] * in[f][a];
-          s1 += tb.Dx[qx * D1 + a] * in[f][a];
+        for (int qx = 0; qx < NQ; ++qx) {
+          x[qx * XQ] = y0[qx];
+          x[XS + qx * XQ] = y1[qx];
         }
-        x[qx * XQ] = s0;
-        x[XS + qx * XQ] = s1;
+      } else {  // high order: full tables, runtime loop (bounded register use)
+#pragma unroll(Unroll<NQ>::full ? NQ : 1)
+        for (int qx = 0; qx < NQ; ++qx) {
+          T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.Dx[qx * D1] * in[f][0];
+#pragma unroll
+          for (int a = 1; a < D1; ++a) {
+            s0 += tb.B[qx * D1 + a] * in[f][a];
+            s1 += tb.Dx[qx * D1 + a] * in[f][a];
+          }
+          x[qx * XQ] = s0;
+          x[XS + qx * XQ] = s1;
+        }
       }
     }
   }
@@ -186,31 +313,99 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
 
 // Phase C forward for one field: y-pass of column (qx,qy) from x-pass slot
 // xs, then z-pass into gf[3][NQ] (reference gradient x, y, z at each qz).
+// The z-pass takes the nodes c and D1-1-c together (even-odd form).
 template <int D1, int NQ, int XQ, class T, class TB>
 __device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const T (&By)[D1],
                                                const T (&Dy)[D1], int qx, T (&gf)[3][NQ]) {
   constexpr int XS = D1 * NQ * XQ;
-#pragma unroll
-  for (int qz = 0; qz < NQ; ++qz) gf[0][qz] = gf[1][qz] = gf[2][qz] = T(0);
-#pragma unroll(Unroll<D1>::full ? D1 : 1)
-  for (int c = 0; c < D1; ++c) {
+  using E = EO<D1, NQ>;
+  // y-pass for this column at node row c: Y0 = D_y X0 (d/dy), Y1 = B_y X0
+  // (d/dz), Y2 = B_y X1 (d/dx)
+  auto ypass = [&](int c, T (&y)[3]) {
     const T* x0 = xs + (c * NQ + qx) * XQ;
     const T* x1 = x0 + XS;
-    // y-pass for this column: Y0 = D_y X0 (d/dy), Y1 = B_y X0 (d/dz), Y2 = B_y X1 (d/dx)
-    T y0 = Dy[0] * x0[0], y1 = By[0] * x0[0], y2 = By[0] * x1[0];
+    y[0] = Dy[0] * x0[0];
+    y[1] = By[0] * x0[0];
+    y[2] = By[0] * x1[0];
 #pragma unroll
     for (int b = 1; b < D1; ++b) {
-      y0 += Dy[b] * x0[b];
-      y1 += By[b] * x0[b];
-      y2 += By[b] * x1[b];
+      y[0] += Dy[b] * x0[b];
+      y[1] += By[b] * x0[b];
+      y[2] += By[b] * x1[b];
     }
-    // z-pass: gx += B_z Y2, gy += B_z Y0, gz += D_z Y1
+  };
+  if constexpr (!Unroll<D1>::full) {
+    // high order: full tables, runtime loop over the node rows (bounded
+    // register use); gx += B_z Y2, gy += B_z Y0, gz += D_z Y1
 #pragma unroll
-    for (int qz = 0; qz < NQ; ++qz) {
-      gf[0][qz] += tb.B[qz * D1 + c] * y2;
-      gf[1][qz] += tb.B[qz * D1 + c] * y0;
-      gf[2][qz] += tb.Dz[qz * D1 + c] * y1;
+    for (int qz = 0; qz < NQ; ++qz) gf[0][qz] = gf[1][qz] = gf[2][qz] = T(0);
+#pragma unroll 1
+    for (int c = 0; c < D1; ++c) {
+      T y[3];
+      ypass(c, y);
+#pragma unroll
+      for (int qz = 0; qz < NQ; ++qz) {
+        gf[0][qz] += tb.B[qz * D1 + c] * y[2];
+        gf[1][qz] += tb.B[qz * D1 + c] * y[0];
+        gf[2][qz] += tb.Dz[qz * D1 + c] * y[1];
+      }
     }
+    return;
+  }
+  // z-pass: gx = B_z Y2, gy = B_z Y0 (symmetric table), gz = D_z Y1
+  // (antisymmetric); s: even parts, d: odd parts, per output pair
+  T s[3][E::QP], d[3][E::QP];
+#pragma unroll
+  for (int q = 0; q < E::QP; ++q) s[0][q] = s[1][q] = s[2][q] = d[0][q] = d[1][q] = d[2][q] = T(0);
+#pragma unroll
+  for (int cp = 0; cp < E::AP; ++cp) {
+    T ya[3], ee[3], oo[3];
+    ypass(cp, ya);
+    if (cp < E::AH) {
+      T yb[3];
+      ypass(D1 - 1 - cp, yb);
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ee[k] = ya[k] + yb[k];
+        oo[k] = ya[k] - yb[k];
+      }
+    } else {  // middle node row (D1 odd)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        ee[k] = ya[k];
+        oo[k] = T(0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < E::QP; ++q) {
+      const T pb = tb.Pb[q * E::AP + cp];
+      s[0][q] += pb * ee[2];
+      s[1][q] += pb * ee[0];
+      if (q < E::QH) s[2][q] += tb.Pz[q * E::AP + cp] * ee[1];
+      if (cp < E::AH) {
+        if (q < E::QH) {
+          const T nb = tb.Nb[q * E::AH + cp];
+          d[0][q] += nb * oo[2];
+          d[1][q] += nb * oo[0];
+        }
+        d[2][q] += tb.Nz[q * E::AH + cp] * oo[1];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < E::QH; ++q) {
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      gf[k][q] = s[k][q] + d[k][q];
+      gf[k][NQ - 1 - q] = s[k][q] - d[k][q];
+    }
+    gf[2][q] = s[2][q] + d[2][q];
+    gf[2][NQ - 1 - q] = d[2][q] - s[2][q];
+  }
+  if constexpr (NQ % 2) {
+    gf[0][E::QH] = s[0][E::QH];
+    gf[1][E::QH] = s[1][E::QH];
+    gf[2][E::QH] = d[2][E::QH];
   }
 }
 
@@ -518,21 +713,41 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
       }
     } else {
       // z-back: H0[c] = sum_qz B Fx, H1 = sum_qz B Fy, H2 = sum_qz D Fz
+      using E = EO<D1, NQ>;
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         T* h = Hs + el * L::HSTR + o * 3 * D1 * NQ2 + qxy;
-#pragma unroll(Unroll<D1>::full ? D1 : 1)
-        for (int c = 0; c < D1; ++c) {
-          T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.Dz[c] * g[o][2][0];
+        if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
+#pragma unroll 1
+          for (int c = 0; c < D1; ++c) {
+            T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.Dz[c] * g[o][2][0];
 #pragma unroll
-          for (int qz = 1; qz < NQ; ++qz) {
-            s0 += tb.B[qz * D1 + c] * g[o][0][qz];
-            s1 += tb.B[qz * D1 + c] * g[o][1][qz];
-            s2 += tb.Dz[qz * D1 + c] * g[o][2][qz];
+            for (int qz = 1; qz < NQ; ++qz) {
+              s0 += tb.B[qz * D1 + c] * g[o][0][qz];
+              s1 += tb.B[qz * D1 + c] * g[o][1][qz];
+              s2 += tb.Dz[qz * D1 + c] * g[o][2][qz];
+            }
+            h[c * NQ2] = s0;
+            h[D1 * NQ2 + c * NQ2] = s1;
+            h[2 * D1 * NQ2 + c * NQ2] = s2;
           }
-          h[c * NQ2] = s0;
-          h[D1 * NQ2 + c * NQ2] = s1;
-          h[2 * D1 * NQ2 + c * NQ2] = s2;
+          continue;
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          T xe[E::QH + 1], xo[E::QH + 1], xm, sp[E::AP], sm[E::AH], y[D1];
+#pragma unroll
+          for (int a = 0; a < E::AP; ++a) sp[a] = T(0);
+#pragma unroll
+          for (int a = 0; a < E::AH; ++a) sm[a] = T(0);
+          eo_pairs<D1, NQ>(g[o][k], xe, xo, xm);
+          if (k < 2)
+            eo_backward_add<D1, NQ, true>(tb.Pb, tb.Nb, xe, xo, xm, sp, sm);
+          else
+            eo_backward_add<D1, NQ, false>(tb.Pz, tb.Nz, xe, xo, xm, sp, sm);
+          eo_backward_finish<D1, NQ>(sp, sm, y);
+#pragma unroll
+          for (int c = 0; c < D1; ++c) h[(k * D1 + c) * NQ2] = y[c];
         }
       }
     }
@@ -589,24 +804,47 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
           k[2 * L::XS + b] = kdb;
         }
       } else {
+        using E = EO<D1, NQ>;
 #pragma unroll
         for (int o = 0; o < O; ++o) {
-          const T(&h0)[NQ] = hv[3 * o];
-          const T(&h1)[NQ] = hv[3 * o + 1];
-          const T(&h2)[NQ] = hv[3 * o + 2];
           T* k = Xs + el * L::XSTR + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
-#pragma unroll(Unroll<D1>::full ? D1 : 1)
-          for (int b = 0; b < D1; ++b) {
-            T s0 = tb.B[b] * h0[0], s1 = tb.Dy[b] * h1[0];
-            s1 += tb.B[b] * h2[0];
+          if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
+            const T(&h0)[NQ] = hv[3 * o];
+            const T(&h1)[NQ] = hv[3 * o + 1];
+            const T(&h2)[NQ] = hv[3 * o + 2];
+#pragma unroll 1
+            for (int b = 0; b < D1; ++b) {
+              T s0 = tb.B[b] * h0[0], s1 = tb.Dy[b] * h1[0];
+              s1 += tb.B[b] * h2[0];
 #pragma unroll
-            for (int qy = 1; qy < NQ; ++qy) {
-              s0 += tb.B[qy * D1 + b] * h0[qy];
-              s1 += tb.Dy[qy * D1 + b] * h1[qy];
-              s1 += tb.B[qy * D1 + b] * h2[qy];
+              for (int qy = 1; qy < NQ; ++qy) {
+                s0 += tb.B[qy * D1 + b] * h0[qy];
+                s1 += tb.Dy[qy * D1 + b] * h1[qy];
+                s1 += tb.B[qy * D1 + b] * h2[qy];
+              }
+              k[b] = s0;
+              k[L::XS + b] = s1;
             }
-            k[b] = s0;
-            k[L::XS + b] = s1;
+            continue;
+          }
+          // K0 = B^T H0; K1 = Dy^T H1 + B^T H2 (even-odd form, one sum for both)
+          T xe[E::QH + 1], xo[E::QH + 1], xm, sp0[E::AP], sm0[E::AH], sp1[E::AP], sm1[E::AH], k0[D1], k1[D1];
+#pragma unroll
+          for (int a = 0; a < E::AP; ++a) sp0[a] = sp1[a] = T(0);
+#pragma unroll
+          for (int a = 0; a < E::AH; ++a) sm0[a] = sm1[a] = T(0);
+          eo_pairs<D1, NQ>(hv[3 * o], xe, xo, xm);
+          eo_backward_add<D1, NQ, true>(tb.Pb, tb.Nb, xe, xo, xm, sp0, sm0);
+          eo_pairs<D1, NQ>(hv[3 * o + 1], xe, xo, xm);
+          eo_backward_add<D1, NQ, false>(tb.Py, tb.Ny, xe, xo, xm, sp1, sm1);
+          eo_pairs<D1, NQ>(hv[3 * o + 2], xe, xo, xm);
+          eo_backward_add<D1, NQ, true>(tb.Pb, tb.Nb, xe, xo, xm, sp1, sm1);
+          eo_backward_finish<D1, NQ>(sp0, sm0, k0);
+          eo_backward_finish<D1, NQ>(sp1, sm1, k1);
+#pragma unroll
+          for (int b = 0; b < D1; ++b) {
+            k[b] = k0[b];
+            k[L::XS + b] = k1[b];
           }
         }
       }
@@ -663,17 +901,34 @@ __global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) 
       }
       // output 0 is the JVP (or residual); output 1 the residual of residual + JVP
       T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) + pos;
-#pragma unroll(Unroll<D1>::full ? D1 : 1)
-      for (int a = 0; a < D1; ++a) {
-        T s = tb.Dx[a] * k0[0];
-        s += tb.B[a] * k1[0];
+      if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
+#pragma unroll 1
+        for (int a = 0; a < D1; ++a) {
+          T s = tb.Dx[a] * k0[0];
+          s += tb.B[a] * k1[0];
 #pragma unroll
-        for (int qx = 1; qx < NQ; ++qx) {
-          s += tb.Dx[qx * D1 + a] * k0[qx];
-          s += tb.B[qx * D1 + a] * k1[qx];
+          for (int qx = 1; qx < NQ; ++qx) {
+            s += tb.Dx[qx * D1 + a] * k0[qx];
+            s += tb.B[qx * D1 + a] * k1[qx];
+          }
+          out[a] = s;
         }
-        out[a] = s;
+        continue;
       }
+      // out = Dx^T K0 + B^T K1 (even-odd form, one sum for both)
+      using E = EO<D1, NQ>;
+      T xe[E::QH + 1], xo[E::QH + 1], xm, sp[E::AP], sm[E::AH], y[D1];
+#pragma unroll
+      for (int a = 0; a < E::AP; ++a) sp[a] = T(0);
+#pragma unroll
+      for (int a = 0; a < E::AH; ++a) sm[a] = T(0);
+      eo_pairs<D1, NQ>(k0, xe, xo, xm);
+      eo_backward_add<D1, NQ, false>(tb.Px, tb.Nx, xe, xo, xm, sp, sm);
+      eo_pairs<D1, NQ>(k1, xe, xo, xm);
+      eo_backward_add<D1, NQ, true>(tb.Pb, tb.Nb, xe, xo, xm, sp, sm);
+      eo_backward_finish<D1, NQ>(sp, sm, y);
+#pragma unroll
+      for (int a = 0; a < D1; ++a) out[a] = y[a];
     }
   }
 }
@@ -694,6 +949,22 @@ Tab<D1, NQ, T> make_tab(const double* h, const double* hs = nullptr) {
     t.w[i] = (T)h[2 * NQ * D1 + i];
     t.xi[i] = (T)h[2 * NQ * D1 + NQ + i];
   }
+  // even-odd forms, computed in FP64 from the (scaled) FP64 tables
+  using E = EO<D1, NQ>;
+  auto eo = [&](const double* M, double scale, T* P, T* N) {
+    for (int q = 0; q < E::QP; ++q) {
+      for (int a = 0; a < E::AH; ++a) {
+        const double m0 = M[q * D1 + a] * scale, m1 = M[q * D1 + D1 - 1 - a] * scale;
+        P[q * E::AP + a] = (T)(0.5 * (m0 + m1));
+        N[q * E::AH + a] = (T)(0.5 * (m0 - m1));
+      }
+      if (D1 % 2) P[q * E::AP + E::AH] = (T)(M[q * D1 + E::AH] * scale);
+    }
+  };
+  eo(h, 1.0, t.Pb, t.Nb);
+  eo(h + NQ * D1, hs ? hs[0] : 1.0, t.Px, t.Nx);
+  eo(h + NQ * D1, hs ? hs[1] : 1.0, t.Py, t.Ny);
+  eo(h + NQ * D1, hs ? hs[2] : 1.0, t.Pz, t.Nz);
   return t;
 }
 
