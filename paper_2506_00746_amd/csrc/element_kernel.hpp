@@ -176,11 +176,12 @@ struct Config {
   // ALIAS2: two-field operations share one LDS region between the phases
   // (see Lds); one-field operations always do.
   static constexpr bool ALIAS2 = true;
-  // WPE: minimum waves per SIMD asked of the register allocator.  At Q4 / nq 6
-  // in FP32 asking for 6 lets the Jacobian kernel fit 67 VGPRs (7 waves) and
-  // runs it 15% faster; elsewhere the default allocation was as fast or
-  // faster (FP64 Q3 spills under the same request).
-  static constexpr int WPE = (D1 == 5 && NQ == 6 && sizeof(T) == 4) ? 6 : 1;
+  // WPE: minimum waves per SIMD asked of the register allocator, for affine
+  // meshes with a specialised exponent (curved and generic-exponent kernels
+  // need more registers and spill under it).  Q4 / nq 6 in FP32: 6 fits the
+  // Jacobian kernel in 67 VGPRs (7 waves), 15% faster.  Q3 / nq 5 in FP64: 5
+  // fits it in 95 VGPRs without spills (5 waves instead of 4).
+  static constexpr int WPE = (D1 == 5 && NQ == 6 && sizeof(T) == 4) ? 6 : ((D1 == 4 && NQ == 5 && sizeof(T) == 8) ? 5 : 1);
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
   static constexpr int NT = 256;
@@ -410,8 +411,8 @@ __device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const 
 }
 
 template <int D1, int NQ, class T, int OP, bool CURVED, int PK>
-__global__ __launch_bounds__((Config<D1, NQ, T>::NT), (Config<D1, NQ, T>::WPE)) void element_kernel(ElemParams P,
-                                                                                                Tab<D1, NQ, T> tb) {
+__global__ __launch_bounds__((Config<D1, NQ, T>::NT), ((CURVED || PK == POW_GENERIC) ? 1 : Config<D1, NQ, T>::WPE))
+void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   using C = Config<D1, NQ, T>;
   constexpr int NT = C::NT;
   constexpr int EB = C::EB;
