@@ -378,6 +378,15 @@ class HostSetup:
             self.emap = self.emap.reshape(E, D1 ** 3)
             self.load = f64(n_dofs)
             _check(L.feod_host_load(ctx, self.load.ctypes.data), ctx)
+            # the library's cost model: (algorithmic bytes, FLOPs) per launch
+            self.cost = {}
+            for op, code in OPS.items():
+                if op == "diag":
+                    continue
+                for prec, pc in PREC.items():
+                    b, f = ctypes.c_double(), ctypes.c_double()
+                    _check(L.feod_kernel_cost(ctx, code, pc, ctypes.byref(b), ctypes.byref(f)), ctx)
+                    self.cost[(op, prec)] = (b.value, f.value)
         finally:
             L.feod_destroy(ctx)
 

@@ -114,3 +114,31 @@ def test_profile_summary_parser_and_source_hash(tmp_path):
     p.write_text(f"# x\n\ntraffic_bytes_per_launch: 3.2e+07\nkernel_source_sha256: {sha}\n")
     assert profiling.read_traffic(str(p)) == (3.2e7, sha)
     assert profiling.read_traffic(str(tmp_path / "missing.md")) == (None, None)
+
+
+def test_cost_model_matches_its_formula():
+    """The roofline's algorithmic counts: FLOPs = E (passes S + nq^3 f_D) with
+    S = 4 nq D1^3 + 6 nq^2 D1^2 + 6 nq^3 D1 per sum-factorised pass, f_D the
+    per-point count of the pointwise operator; bytes = unique L-vector reads
+    + E-vector writes (+ rho, vertices, stored gradients where used)."""
+    from workloads import WORKLOADS, make_inputs
+    cases = {"c2": ("jvp", 2 + 17 + 9 + 0 + 4),          # affine, r = 1
+             "c4": ("jvp", 2 + 17 + 9 + 12 + 4),         # affine, r = 1/2
+             "c5": ("jvp", 2 + 17 + 9 + 12 + 99)}        # curved, r = 1/2
+    for name, (op, f_d) in cases.items():
+        w = WORKLOADS[name]
+        inp = make_inputs(w)
+        hs = feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=inp["vertices"], rho=inp["rho"])
+        d1, nq, e, n = w.k + 1, w.nq, w.n_elems, w.n_dofs
+        s = 4 * nq * d1 ** 3 + 6 * nq ** 2 * d1 ** 2 + 6 * nq ** 3 * d1
+        flops = e * (3 * s + nq ** 3 * f_d)
+        nbytes = 2 * 8.0 * n + 8.0 * e * d1 ** 3
+        if inp["rho"] is not None:
+            nbytes += 8.0 * e
+        if inp["vertices"] is not None:
+            nbytes += 24.0 * (w.nx + 1) * (w.ny + 1) * (w.nz + 1)
+        b, f = hs.cost[(op, "fp64")]
+        assert f == pytest.approx(flops, rel=1e-14), name
+        assert b == pytest.approx(nbytes, rel=1e-14), name
+        b32, f32 = hs.cost[(op, "mixed")]
+        assert f32 == f and b32 == pytest.approx(nbytes - 4.0 * e * d1 ** 3, rel=1e-14)
