@@ -322,7 +322,9 @@ __global__ __launch_bounds__(kGatherDotThreads) void gather_t_dot_kernel(const i
                                                                          double* __restrict__ partial) {
   double acc = 0;
   const int64_t stride = (int64_t)gridDim.x * kGatherDotThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kGatherDotThreads + threadIdx.x; i < n; i += stride) {
+  // same DOF-to-block assignment as the lattice kernel: bitwise-equal partials
+  for (int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kGatherDotThreads + threadIdx.x; i < n;
+       i += stride) {
     double s = 0;
     for (int j = off[i]; j < off[i + 1]; ++j) s += (double)Y[idx[j]];
     q[i] = s;

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 import torch
 
+import paper_2506_00746_amd as feod
 from tests.gpu_helpers import announce, dev, host, relerr, setup
 from workloads import WORKLOADS, Workload, make_inputs
 
@@ -147,6 +148,17 @@ def test_lattice_and_explicit_maps_bitwise_equal(w):
         rm = prob.residual(u, prec="mixed")
         outs[mode] = [host(r), host(jv), host(rm), host(prob.jacobian_apply(u, v))]
     for a, b in zip(outs["lattice"], outs["explicit"]):
+        assert np.array_equal(a, b)
+    # the CG solves (fused G^T + p.q) give bitwise the same iterates too
+    load = dev(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load)
+    sols = {}
+    for mode in ("lattice", "explicit"):
+        prob.set_map_mode(mode)
+        un, rep = prob.newton_solve(rtol=1e-10)
+        g, lam, arep = prob.adjoint_gradient(un, load, rtol=1e-10)
+        gm, _, _ = prob.adjoint_gradient(un, load, rtol=1e-10, prec="mixed")
+        sols[mode] = [host(un), host(g), host(lam), host(gm)]
+    for a, b in zip(sols["lattice"], sols["explicit"]):
         assert np.array_equal(a, b)
 
 
