@@ -20,11 +20,86 @@
 
 namespace feod {
 
+// One (d, d') tensor term: x stage (through LDS) into T1, then the y stage
+// added into T2.  In the y stage a thread owns one (qz, a, a') and all
+// (b, b') outputs: each T1 value is read once and the 1D factors are the
+// same LDS word for every lane.
+template <int D1, int NQ, int NT, int d, int d2, class T>
+__device__ __forceinline__ void tangent_term(const Tab<D1, NQ, T>& tb, const T* sB, const T* sD, const T* Cdd,
+                                             T* sT1, T* sT2, int tid) {
+  constexpr int D2 = D1 * D1, D4 = D2 * D2;
+  const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
+  const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
+  // 1D factors in y: the same LDS word for every lane (broadcast reads)
+  const T* Fy0 = d == 1 ? sD : sB;
+  const T* Fy1 = d2 == 1 ? sD : sB;
+  // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
+  for (int i = tid; i < NQ * NQ * D2; i += NT) {
+    const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
+    T sacc = 0;
+    for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
+    sT1[i] = sacc;
+  }
+  __syncthreads();
+  // y: T2[qz][b][b'][a][a'] += sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
+  for (int t = tid; t < NQ * D2; t += NT) {
+    const int qz = t / D2, aa = t - qz * D2;
+    T t1[NQ];
+#pragma unroll
+    for (int qy = 0; qy < NQ; ++qy) t1[qy] = sT1[(qz * NQ + qy) * D2 + aa];
+#pragma unroll
+    for (int b = 0; b < D1; ++b) {
+      T u[NQ];
+#pragma unroll
+      for (int qy = 0; qy < NQ; ++qy) u[qy] = Fy0[qy * D1 + b] * t1[qy];
+#pragma unroll
+      for (int b2 = 0; b2 < D1; ++b2) {
+        T sacc = Fy1[b2] * u[0];
+#pragma unroll
+        for (int qy = 1; qy < NQ; ++qy) sacc += Fy1[qy * D1 + b2] * u[qy];
+        sT2[qz * D4 + (b * D1 + b2) * D2 + aa] += sacc;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// z stage of one z-factor group: K[c][c'][ab] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][ab],
+// a thread owning ab (and all (c, c')) with the factors in scalar registers.
+template <int D1, int NQ, int NT, bool zd0, bool zd1, class T>
+__device__ __forceinline__ void tangent_zstage(const Tab<D1, NQ, T>& tb, const T* sT2, int tid,
+                                               T (&acc)[(D1 * D1 * D1 * D1 + NT - 1) / NT][D1 * D1]) {
+  constexpr int D4 = D1 * D1 * D1 * D1, SL = (D4 + NT - 1) / NT;
+  auto Fz0 = [&](int i) -> T {
+    if constexpr (zd0) return tb.Dx[i];
+    else return tb.B[i];
+  };
+  auto Fz1 = [&](int i) -> T {
+    if constexpr (zd1) return tb.Dx[i];
+    else return tb.B[i];
+  };
+#pragma unroll
+  for (int sl = 0; sl < SL; ++sl) {
+    const int ab = tid + sl * NT;
+    if (ab < D4) {
+#pragma unroll
+      for (int qz = 0; qz < NQ; ++qz) {
+        const T t2 = sT2[qz * D4 + ab];
+#pragma unroll
+        for (int c = 0; c < D1; ++c) {
+          const T u = Fz0(qz * D1 + c) * t2;
+#pragma unroll
+          for (int c2 = 0; c2 < D1; ++c2) acc[sl][c * D1 + c2] += Fz1(qz * D1 + c2) * u;
+        }
+      }
+    }
+  }
+}
+
 template <int D1, int NQ, class T, bool CURVED, int PK>
 __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   constexpr int NT = 256;
   constexpr int Ne = D1 * D1 * D1, NQ3 = NQ * NQ * NQ, NE2 = Ne * Ne;
-  constexpr int PER = (NE2 + NT - 1) / NT;
   constexpr int D2 = D1 * D1, D4 = D2 * D2;
   __shared__ T sU[Ne];
   __shared__ T sG[3][NQ3];
@@ -133,66 +208,51 @@ __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, 
   }
   __syncthreads();
 
-  T acc[PER];
+  constexpr int SL = (D4 + NT - 1) / NT;
+  T acc[SL][D2];
 #pragma unroll
-  for (int m = 0; m < PER; ++m) acc[m] = 0;
+  for (int sl = 0; sl < SL; ++sl)
+#pragma unroll
+    for (int cc = 0; cc < D2; ++cc) acc[sl][cc] = 0;
   // The z factor of psi_d is D for d = 2 and B otherwise, so the nine (d,d')
   // terms fall into four groups by their z-factor pair; the z stage is linear,
   // so each group's y-stage outputs are summed first and contracted in z once.
-  for (int zg = 0; zg < 4; ++zg) {
-    const bool zd0 = zg & 1, zd1 = zg >> 1;  // z factor of psi_d / psi_d' is D
+  auto clear_t2 = [&] {
     for (int i = tid; i < NQ * D4; i += NT) sT2[i] = 0;
-    for (int d = 0; d < 3; ++d) {
-      if ((d == 2) != zd0) continue;
-      for (int d2 = 0; d2 < 3; ++d2) {
-        if ((d2 == 2) != zd1) continue;
-        const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
-        const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
-        const T* Fy0 = d == 1 ? sD : sB;
-        const T* Fy1 = d2 == 1 ? sD : sB;
-        const T* Cdd = sC[d * 3 + d2];
-        // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
-        for (int i = tid; i < NQ * NQ * D2; i += NT) {
-          const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
-          T sacc = 0;
-          for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
-          sT1[i] = sacc;
-        }
-        __syncthreads();
-        // y: T2[qz][b][b'][a][a'] += sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
-        for (int i = tid; i < NQ * D4; i += NT) {
-          const int aa = i % D2, bb = (i / D2) % D2, qz = i / D4, b = bb / D1, b2 = bb % D1;
-          T sacc = 0;
-          for (int qy = 0; qy < NQ; ++qy) sacc += Fy0[qy * D1 + b] * Fy1[qy * D1 + b2] * sT1[(qz * NQ + qy) * D2 + aa];
-          sT2[i] += sacc;
-        }
-        __syncthreads();
-      }
-    }
-    // z: K[c][c'][b][b'][a][a'] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][b][b'][a][a']
-    const T* Fz0 = zd0 ? sD : sB;
-    const T* Fz1 = zd1 ? sD : sB;
-#pragma unroll
-    for (int m = 0; m < PER; ++m) {
-      const int L = tid + m * NT;
-      if (L < NE2) {
-        const int ab = L % D4, cc = L / D4, c = cc / D1, c2 = cc % D1;
-        T sacc = 0;
-        for (int qz = 0; qz < NQ; ++qz) sacc += Fz0[qz * D1 + c] * Fz1[qz * D1 + c2] * sT2[qz * D4 + ab];
-        acc[m] += sacc;
-      }
-    }
-    __syncthreads();
-  }
-  // K_e row i = a + D1 (b + D1 c), column j = a' + D1 (b' + D1 c'), row-major
+  };
+  clear_t2();  // the first x stage's barrier orders this before the y stage
+  tangent_term<D1, NQ, NT, 0, 0>(tb, sB, sD, sC[0], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 0, 1>(tb, sB, sD, sC[1], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 0>(tb, sB, sD, sC[3], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 1>(tb, sB, sD, sC[4], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, false, false>(tb, sT2, tid, acc);
+  __syncthreads();
+  clear_t2();
+  tangent_term<D1, NQ, NT, 2, 0>(tb, sB, sD, sC[6], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 2, 1>(tb, sB, sD, sC[7], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, true, false>(tb, sT2, tid, acc);
+  __syncthreads();
+  clear_t2();
+  tangent_term<D1, NQ, NT, 0, 2>(tb, sB, sD, sC[2], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 2>(tb, sB, sD, sC[5], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, false, true>(tb, sT2, tid, acc);
+  __syncthreads();
+  clear_t2();
+  tangent_term<D1, NQ, NT, 2, 2>(tb, sB, sD, sC[8], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, true, true>(tb, sT2, tid, acc);
+  // K_e row i = a + D1 (b + D1 c), column j = a' + D1 (b' + D1 c'), row-major;
+  // ab = (b D1 + b') D2 + (a D1 + a'), cc = c D1 + c'
   T* Ke = static_cast<T*>(P.out0) + (int64_t)blockIdx.x * NE2;
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int L = tid + m * NT;
-    if (L < NE2) {
-      const int a2 = L % D1, a = (L / D1) % D1, b2 = (L / D2) % D1, b = (L / (D2 * D1)) % D1;
-      const int c2 = (L / D4) % D1, c = L / (D4 * D1);
-      Ke[(a + D1 * (b + D1 * c)) * Ne + (a2 + D1 * (b2 + D1 * c2))] = acc[m];
+  for (int sl = 0; sl < SL; ++sl) {
+    const int ab = tid + sl * NT;
+    if (ab < D4) {
+      const int aa = ab % D2, bb = ab / D2, a = aa / D1, a2 = aa % D1, b = bb / D1, b2 = bb % D1;
+#pragma unroll
+      for (int cc = 0; cc < D2; ++cc) {
+        const int c = cc / D1, c2 = cc % D1;
+        Ke[(a + D1 * (b + D1 * c)) * Ne + (a2 + D1 * (b2 + D1 * c2))] = acc[sl][cc];
+      }
     }
   }
 }
