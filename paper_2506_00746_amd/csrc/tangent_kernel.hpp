@@ -25,8 +25,7 @@ namespace feod {
 // (b, b') outputs: each T1 value is read once and the 1D factors are the
 // same LDS word for every lane.
 template <int D1, int NQ, int NT, int d, int d2, class T>
-__device__ __forceinline__ void tangent_term(const Tab<D1, NQ, T>& tb, const T* sB, const T* sD, const T* Cdd,
-                                             T* sT1, T* sT2, int tid) {
+__device__ __forceinline__ void tangent_term(const T* sB, const T* sD, const T* Cdd, T* sT1, T* sT2, int tid) {
   constexpr int D2 = D1 * D1, D4 = D2 * D2;
   const T* Fx0 = d == 0 ? sD : sB;   // factor of psi_d in x
   const T* Fx1 = d2 == 0 ? sD : sB;  // factor of psi_d' in x
@@ -65,19 +64,13 @@ __device__ __forceinline__ void tangent_term(const Tab<D1, NQ, T>& tb, const T* 
 }
 
 // z stage of one z-factor group: K[c][c'][ab] += sum_qz Fz0[qz][c] Fz1[qz][c'] T2[qz][ab],
-// a thread owning ab (and all (c, c')) with the factors in scalar registers.
+// a thread owning ab and all (c, c'): each T2 value is read once.
 template <int D1, int NQ, int NT, bool zd0, bool zd1, class T>
-__device__ __forceinline__ void tangent_zstage(const Tab<D1, NQ, T>& tb, const T* sT2, int tid,
+__device__ __forceinline__ void tangent_zstage(const T* sB, const T* sD, const T* sT2, int tid,
                                                T (&acc)[(D1 * D1 * D1 * D1 + NT - 1) / NT][D1 * D1]) {
   constexpr int D4 = D1 * D1 * D1 * D1, SL = (D4 + NT - 1) / NT;
-  auto Fz0 = [&](int i) -> T {
-    if constexpr (zd0) return tb.Dx[i];
-    else return tb.B[i];
-  };
-  auto Fz1 = [&](int i) -> T {
-    if constexpr (zd1) return tb.Dx[i];
-    else return tb.B[i];
-  };
+  const T* Fz0 = zd0 ? sD : sB;  // the same LDS word for every lane (broadcast)
+  const T* Fz1 = zd1 ? sD : sB;
 #pragma unroll
   for (int sl = 0; sl < SL; ++sl) {
     const int ab = tid + sl * NT;
@@ -87,9 +80,9 @@ __device__ __forceinline__ void tangent_zstage(const Tab<D1, NQ, T>& tb, const T
         const T t2 = sT2[qz * D4 + ab];
 #pragma unroll
         for (int c = 0; c < D1; ++c) {
-          const T u = Fz0(qz * D1 + c) * t2;
+          const T u = Fz0[qz * D1 + c] * t2;
 #pragma unroll
-          for (int c2 = 0; c2 < D1; ++c2) acc[sl][c * D1 + c2] += Fz1(qz * D1 + c2) * u;
+          for (int c2 = 0; c2 < D1; ++c2) acc[sl][c * D1 + c2] += Fz1[qz * D1 + c2] * u;
         }
       }
     }
@@ -221,25 +214,25 @@ __global__ __launch_bounds__(256) void tangent_kernel(ElemParams P, Tab<D1, NQ, 
     for (int i = tid; i < NQ * D4; i += NT) sT2[i] = 0;
   };
   clear_t2();  // the first x stage's barrier orders this before the y stage
-  tangent_term<D1, NQ, NT, 0, 0>(tb, sB, sD, sC[0], sT1, sT2, tid);
-  tangent_term<D1, NQ, NT, 0, 1>(tb, sB, sD, sC[1], sT1, sT2, tid);
-  tangent_term<D1, NQ, NT, 1, 0>(tb, sB, sD, sC[3], sT1, sT2, tid);
-  tangent_term<D1, NQ, NT, 1, 1>(tb, sB, sD, sC[4], sT1, sT2, tid);
-  tangent_zstage<D1, NQ, NT, false, false>(tb, sT2, tid, acc);
+  tangent_term<D1, NQ, NT, 0, 0>(sB, sD, sC[0], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 0, 1>(sB, sD, sC[1], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 0>(sB, sD, sC[3], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 1>(sB, sD, sC[4], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, false, false>(sB, sD, sT2, tid, acc);
   __syncthreads();
   clear_t2();
-  tangent_term<D1, NQ, NT, 2, 0>(tb, sB, sD, sC[6], sT1, sT2, tid);
-  tangent_term<D1, NQ, NT, 2, 1>(tb, sB, sD, sC[7], sT1, sT2, tid);
-  tangent_zstage<D1, NQ, NT, true, false>(tb, sT2, tid, acc);
+  tangent_term<D1, NQ, NT, 2, 0>(sB, sD, sC[6], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 2, 1>(sB, sD, sC[7], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, true, false>(sB, sD, sT2, tid, acc);
   __syncthreads();
   clear_t2();
-  tangent_term<D1, NQ, NT, 0, 2>(tb, sB, sD, sC[2], sT1, sT2, tid);
-  tangent_term<D1, NQ, NT, 1, 2>(tb, sB, sD, sC[5], sT1, sT2, tid);
-  tangent_zstage<D1, NQ, NT, false, true>(tb, sT2, tid, acc);
+  tangent_term<D1, NQ, NT, 0, 2>(sB, sD, sC[2], sT1, sT2, tid);
+  tangent_term<D1, NQ, NT, 1, 2>(sB, sD, sC[5], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, false, true>(sB, sD, sT2, tid, acc);
   __syncthreads();
   clear_t2();
-  tangent_term<D1, NQ, NT, 2, 2>(tb, sB, sD, sC[8], sT1, sT2, tid);
-  tangent_zstage<D1, NQ, NT, true, true>(tb, sT2, tid, acc);
+  tangent_term<D1, NQ, NT, 2, 2>(sB, sD, sC[8], sT1, sT2, tid);
+  tangent_zstage<D1, NQ, NT, true, true>(sB, sD, sT2, tid, acc);
   // K_e row i = a + D1 (b + D1 c), column j = a' + D1 (b' + D1 c'), row-major;
   // ab = (b D1 + b') D2 + (a D1 + a'), cc = c D1 + c'
   T* Ke = static_cast<T*>(P.out0) + (int64_t)blockIdx.x * NE2;
