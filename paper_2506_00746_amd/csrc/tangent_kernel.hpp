@@ -32,12 +32,20 @@ __device__ __forceinline__ void tangent_term(const T* sB, const T* sD, const T* 
   // 1D factors in y: the same LDS word for every lane (broadcast reads)
   const T* Fy0 = d == 1 ? sD : sB;
   const T* Fy1 = d2 == 1 ? sD : sB;
-  // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz)
-  for (int i = tid; i < NQ * NQ * D2; i += NT) {
-    const int aa = i % D2, qyz = i / D2, a = aa / D1, a2 = aa % D1;
-    T sacc = 0;
-    for (int qx = 0; qx < NQ; ++qx) sacc += Fx0[qx * D1 + a] * Fx1[qx * D1 + a2] * Cdd[qx + NQ * qyz];
-    sT1[i] = sacc;
+  // x: T1[qz][qy][a][a'] = sum_qx Fx0[qx][a] Fx1[qx][a'] C(qx,qy,qz); a thread
+  // owns (qy, qz, a) and all a', reading each C value once
+  for (int t = tid; t < NQ * NQ * D1; t += NT) {
+    const int qyz = t / D1, a = t - qyz * D1;
+    T u[NQ];
+#pragma unroll
+    for (int qx = 0; qx < NQ; ++qx) u[qx] = Fx0[qx * D1 + a] * Cdd[qx + NQ * qyz];
+#pragma unroll
+    for (int a2 = 0; a2 < D1; ++a2) {
+      T sacc = Fx1[a2] * u[0];
+#pragma unroll
+      for (int qx = 1; qx < NQ; ++qx) sacc += Fx1[qx * D1 + a2] * u[qx];
+      sT1[qyz * D2 + a * D1 + a2] = sacc;
+    }
   }
   __syncthreads();
   // y: T2[qz][b][b'][a][a'] += sum_qy Fy0[qy][b] Fy1[qy][b'] T1[qz][qy][a][a']
