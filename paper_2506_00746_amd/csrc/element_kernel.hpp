@@ -182,8 +182,15 @@ struct Config {
   // Jacobian kernel in 67 VGPRs (7 waves), 15% faster.  Q3 / nq 5 in FP64: 5
   // fits it in 95 VGPRs without spills (5 waves instead of 4).
   static constexpr int WPE = (D1 == 5 && NQ == 6 && sizeof(T) == 4) ? 6 : ((D1 == 4 && NQ == 5 && sizeof(T) == 8) ? 5 : 1);
+  // RU, RUQ: unroll factors of the runtime loops of high-order kernels
+  static constexpr int RU = 1, RUQ = 1;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
+  // The runtime loops over node rows (RU, 8 iterations) and points (RUQ, 9)
+  // are unrolled by 2 and 3: each iteration waits for its table slice (scalar
+  // loads) and LDS reads, and two or three in flight hide that wait at the
+  // two waves per SIMD these kernels run at.  Fully unrolled they spill.
+  static constexpr int RU = 2, RUQ = 3;
   static constexpr int NT = 256;
   static constexpr int EB = 3;
   static constexpr bool SEQ = true;
@@ -296,7 +303,7 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
           x[XS + qx * XQ] = y1[qx];
         }
       } else {  // high order: full tables, runtime loop (bounded register use)
-#pragma unroll(Unroll<NQ>::full ? NQ : 1)
+#pragma unroll(Unroll<NQ>::full ? NQ : Config<D1, NQ, T>::RUQ)
         for (int qx = 0; qx < NQ; ++qx) {
           T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.Dx[qx * D1] * in[f][0];
 #pragma unroll
@@ -340,7 +347,7 @@ __device__ __forceinline__ void column_forward(const TB& tb, const T* xs, const 
     // register use); gx += B_z Y2, gy += B_z Y0, gz += D_z Y1
 #pragma unroll
     for (int qz = 0; qz < NQ; ++qz) gf[0][qz] = gf[1][qz] = gf[2][qz] = T(0);
-#pragma unroll 1
+#pragma unroll(Config<D1, NQ, T>::RU)
     for (int c = 0; c < D1; ++c) {
       T y[3];
       ypass(c, y);
@@ -719,7 +726,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       for (int o = 0; o < O; ++o) {
         T* h = Hs + el * L::HSTR + o * 3 * D1 * NQ2 + qxy;
         if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
-#pragma unroll 1
+#pragma unroll(Config<D1, NQ, T>::RU)
           for (int c = 0; c < D1; ++c) {
             T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.Dz[c] * g[o][2][0];
 #pragma unroll
@@ -813,7 +820,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
             const T(&h0)[NQ] = hv[3 * o];
             const T(&h1)[NQ] = hv[3 * o + 1];
             const T(&h2)[NQ] = hv[3 * o + 2];
-#pragma unroll 1
+#pragma unroll(Config<D1, NQ, T>::RU)
             for (int b = 0; b < D1; ++b) {
               T s0 = tb.B[b] * h0[0], s1 = tb.Dy[b] * h1[0];
               s1 += tb.B[b] * h2[0];
@@ -903,7 +910,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       // output 0 is the JVP (or residual); output 1 the residual of residual + JVP
       T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) + pos;
       if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
-#pragma unroll 1
+#pragma unroll(Config<D1, NQ, T>::RU)
         for (int a = 0; a < D1; ++a) {
           T s = tb.Dx[a] * k0[0];
           s += tb.B[a] * k1[0];
