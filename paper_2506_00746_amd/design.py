@@ -24,6 +24,7 @@ class DesignSolve(torch.autograd.Function):
         ctx.problem = problem
         ctx.opts = opts
         ctx.report = rep
+        ctx.rho_meta = (rho.dtype, rho.device)
         ctx.save_for_backward(u)
         return u
 
@@ -32,5 +33,7 @@ class DesignSolve(torch.autograd.Function):
         (u,) = ctx.saved_tensors
         opts = {k: v for k, v in ctx.opts.items()
                 if k in ("rtol", "max_cg", "check_every", "prec", "jacobi", "partial_assembly")}
-        grad_rho, _, _ = ctx.problem.adjoint_gradient(u, grad_u.contiguous().to(torch.float64), **opts)
-        return grad_rho, None, None
+        g_u = grad_u.to(device=u.device, dtype=torch.float64).contiguous()
+        grad_rho, _, _ = ctx.problem.adjoint_gradient(u, g_u, **opts)
+        dtype, device = ctx.rho_meta
+        return grad_rho.to(device=device, dtype=dtype), None, None

@@ -137,9 +137,13 @@ def default_opts(**kw) -> SolverOpts:
     return o
 
 
-def _dptr(t: torch.Tensor, n: int, name: str) -> int:
+def _dptr(t: torch.Tensor, n: int, name: str, device: torch.device | None = None) -> int:
+    """Device address of a contiguous float64 GPU tensor of n entries (on
+    ``device`` when given: the library's kernels run on its context's GPU)."""
     if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
         raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, the problem on {device}")
     if not t.is_contiguous() or t.numel() != n:
         raise ValueError(f"{name} must be contiguous with {n} entries")
     return t.data_ptr()
@@ -208,8 +212,11 @@ class Problem:
     def _vec(self, out=None):
         if out is None:
             return torch.empty(self.n_dofs, dtype=torch.float64, device=self.device)
-        _dptr(out, self.n_dofs, "out")
+        self._ptr(out, self.n_dofs, "out")
         return out
+
+    def _ptr(self, t, n, name):
+        return _dptr(t, n, name, self.device)
 
     def _sync_stream(self):
         lib().feod_set_stream(self._ctx, ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream))
@@ -222,7 +229,7 @@ class Problem:
     def residual(self, u, out=None, prec="fp64"):
         out = self._vec(out)
         self._sync_stream()
-        _check(lib().feod_residual(self._ctx, _dptr(u, self.n_dofs, "u"), out.data_ptr(), PREC[prec]),
+        _check(lib().feod_residual(self._ctx, self._ptr(u, self.n_dofs, "u"), out.data_ptr(), PREC[prec]),
                self._ctx)
         return out
 
@@ -230,10 +237,10 @@ class Problem:
         out = self._vec(out)
         rp = None
         if residual_out is not None:
-            rp = _dptr(residual_out, self.n_dofs, "residual_out")
+            rp = self._ptr(residual_out, self.n_dofs, "residual_out")
         self._sync_stream()
-        _check(lib().feod_jacobian_apply(self._ctx, _dptr(u, self.n_dofs, "u"),
-                                         _dptr(v, self.n_dofs, "v"), out.data_ptr(), rp, PREC[prec]),
+        _check(lib().feod_jacobian_apply(self._ctx, self._ptr(u, self.n_dofs, "u"),
+                                         self._ptr(v, self.n_dofs, "v"), out.data_ptr(), rp, PREC[prec]),
                self._ctx)
         return out
 
@@ -245,9 +252,9 @@ class Problem:
     def element_vectors(self, op: str, u, v=None, prec="fp64"):
         """Run only the element kernel (G, B, D, B^T) into the internal E-vector."""
         self._sync_stream()
-        vp = None if v is None else _dptr(v, self.n_dofs, "v")
+        vp = None if v is None else self._ptr(v, self.n_dofs, "v")
         _check(lib().feod_element_vectors(self._ctx, {"residual": 0, "jvp": 1, "resjvp": 2}[op],
-                                          _dptr(u, self.n_dofs, "u"), vp, PREC[prec]), self._ctx)
+                                          self._ptr(u, self.n_dofs, "u"), vp, PREC[prec]), self._ctx)
 
     def element_tangents(self, u, first=0, count=None, out=None):
         """K_e (Eq. 3) for elements first..first+count-1: (count, Ne, Ne) FP64."""
@@ -255,64 +262,65 @@ class Problem:
         ne = (self.k + 1) ** 3
         if out is None:
             out = torch.empty((count, ne, ne), dtype=torch.float64, device=self.device)
-        if out.dtype != torch.float64 or not out.is_contiguous() or out.numel() != count * ne * ne:
-            raise ValueError("out must be a contiguous float64 tensor of count * Ne * Ne entries")
+        op = self._ptr(out, count * ne * ne, "out")
         self._sync_stream()
-        _check(lib().feod_element_tangents(self._ctx, _dptr(u, self.n_dofs, "u"), first, count,
-                                           out.data_ptr()), self._ctx)
+        _check(lib().feod_element_tangents(self._ctx, self._ptr(u, self.n_dofs, "u"), first, count, op),
+               self._ctx)
         return out
 
     def pa_setup(self, u, prec="fp64"):
         """Partial assembly: store the reference gradients of M u at all points."""
         self._sync_stream()
-        _check(lib().feod_pa_setup(self._ctx, _dptr(u, self.n_dofs, "u"), PREC[prec]), self._ctx)
+        _check(lib().feod_pa_setup(self._ctx, self._ptr(u, self.n_dofs, "u"), PREC[prec]), self._ctx)
 
     def jacobian_apply_pa(self, v, out=None, prec="fp64"):
         """J(u) v at the u of the last pa_setup (same precision)."""
         out = self._vec(out)
         self._sync_stream()
-        _check(lib().feod_jacobian_apply_pa(self._ctx, _dptr(v, self.n_dofs, "v"), out.data_ptr(), PREC[prec]),
+        _check(lib().feod_jacobian_apply_pa(self._ctx, self._ptr(v, self.n_dofs, "v"), out.data_ptr(), PREC[prec]),
                self._ctx)
         return out
 
     def energy(self, u):
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         self._sync_stream()
-        _check(lib().feod_energy(self._ctx, _dptr(u, self.n_dofs, "u"), e.data_ptr()), self._ctx)
+        _check(lib().feod_energy(self._ctx, self._ptr(u, self.n_dofs, "u"), e.data_ptr()), self._ctx)
         return e
 
     def jacobian_diagonal(self, u, out=None, prec="fp64"):
         out = self._vec(out)
         self._sync_stream()
-        _check(lib().feod_jacobian_diagonal(self._ctx, _dptr(u, self.n_dofs, "u"), out.data_ptr(),
+        _check(lib().feod_jacobian_diagonal(self._ctx, self._ptr(u, self.n_dofs, "u"), out.data_ptr(),
                                             PREC[prec]), self._ctx)
         return out
 
     def grad_rho(self, u, lam, out=None, prec="fp64"):
         if out is None:
             out = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
-        _dptr(out, self.n_elems, "out")
+        self._ptr(out, self.n_elems, "out")
         self._sync_stream()
-        _check(lib().feod_grad_rho(self._ctx, _dptr(u, self.n_dofs, "u"), _dptr(lam, self.n_dofs, "lambda"),
+        _check(lib().feod_grad_rho(self._ctx, self._ptr(u, self.n_dofs, "u"), self._ptr(lam, self.n_dofs, "lambda"),
                                    out.data_ptr(), PREC[prec]), self._ctx)
         return out
 
     def set_rho(self, rho):
         rho = rho.detach().to(device=self.device, dtype=torch.float64).contiguous()
         self._sync_stream()
-        _check(lib().feod_set_rho(self._ctx, _dptr(rho, self.n_elems, "rho")), self._ctx)
+        _check(lib().feod_set_rho(self._ctx, self._ptr(rho, self.n_elems, "rho")), self._ctx)
         self._rho_keep = rho  # stream-ordered copy; keep alive until it ran
 
     # -- solvers -----------------------------------------------------------
     def newton_solve(self, u0=None, **opts):
+        """Newton-CG from the p = 2 solution (u0 None) or from u0 (then the
+        Poisson start is off unless init_poisson=1 is passed, which discards u0)."""
         o = default_opts(**opts)
         u = torch.zeros(self.n_dofs, dtype=torch.float64, device=self.device) if u0 is None \
-            else u0.detach().clone().to(torch.float64)
-        if u0 is None and "init_poisson" not in opts:
-            o.init_poisson = 1
+            else u0.detach().to(device=self.device, dtype=torch.float64).clone()
+        if "init_poisson" not in opts:
+            o.init_poisson = 1 if u0 is None else 0
         rep = SolverReport()
         self._sync_stream()
-        st = lib().feod_newton_solve(self._ctx, _dptr(u, self.n_dofs, "u"), ctypes.byref(o), ctypes.byref(rep))
+        st = lib().feod_newton_solve(self._ctx, self._ptr(u, self.n_dofs, "u"), ctypes.byref(o), ctypes.byref(rep))
         _check(st, self._ctx)
         return u, rep.as_dict()
 
@@ -322,7 +330,7 @@ class Problem:
         grad = torch.empty(self.n_elems, dtype=torch.float64, device=self.device)
         rep = SolverReport()
         self._sync_stream()
-        st = lib().feod_adjoint_gradient(self._ctx, _dptr(u, self.n_dofs, "u"), _dptr(g_u, self.n_dofs, "g_u"),
+        st = lib().feod_adjoint_gradient(self._ctx, self._ptr(u, self.n_dofs, "u"), self._ptr(g_u, self.n_dofs, "g_u"),
                                          lam.data_ptr(), grad.data_ptr(), ctypes.byref(o), ctypes.byref(rep))
         _check(st, self._ctx)
         return grad, lam, rep.as_dict()

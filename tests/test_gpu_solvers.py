@@ -122,3 +122,30 @@ def test_partial_assembly_solves_match_fused():
     g0, _, _ = prob.adjoint_gradient(u1, b, rtol=1e-12, partial_assembly=0)
     g1, _, _ = prob.adjoint_gradient(u1, b, rtol=1e-12, partial_assembly=1)
     assert relerr(host(g1), host(g0)) <= 1e-10
+
+
+def test_binding_argument_handling():
+    """A u0 given without init_poisson is the Newton start (a converged one
+    takes zero steps); a float32 design variable gets a float32 gradient equal
+    to the FP64 one; a host output tensor is rejected before any launch."""
+    w = Workload("bind", 3, 3, 2, 2, 3, 3.0, 1e-2, 34, perturb=True, rho=True)
+    announce("binding arguments", w)
+    prob, ora, inp = setup(w)
+    u, rep = prob.newton_solve(rtol=1e-12)
+    u2, rep2 = prob.newton_solve(u, rtol=1e-12)
+    assert rep2["newton_iters"] == 0 and rep2["cg_iters_total"] == 0
+    assert torch.equal(u, u2)
+    # float32 rho: the gradient comes back in rho's dtype and device
+    b = dev(ora.b)
+    rho64 = torch.as_tensor(inp["rho"], device="cuda:0").requires_grad_(True)
+    torch.dot(b, feod.DesignSolve.apply(rho64, prob, {"rtol": 1e-13})).backward()
+    rho32 = torch.as_tensor(inp["rho"], device="cuda:0").float().requires_grad_(True)
+    torch.dot(b, feod.DesignSolve.apply(rho32, prob, {"rtol": 1e-13})).backward()
+    assert rho32.grad.dtype == torch.float32 and rho32.grad.device == rho32.device
+    # rho32 rounds rho, so the two gradients agree to FP32 input precision
+    assert relerr(rho32.grad.double().cpu().numpy(), rho64.grad.cpu().numpy()) <= 1e-5
+    ne = (w.k + 1) ** 3
+    with pytest.raises(TypeError):
+        prob.element_tangents(u, 0, 1, out=torch.empty((1, ne, ne), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        prob.element_tangents(u, 0, 2, out=torch.empty((1, ne, ne), dtype=torch.float64, device="cuda:0"))
