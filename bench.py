@@ -360,7 +360,7 @@ def main():
                     help="run one 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the subdomain operator P is the identity on one GPU).", file=sys.stderr)
         sys.exit(2)
 
