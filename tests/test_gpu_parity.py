@@ -227,3 +227,53 @@ def test_partial_assembly_jvp_equals_fused(w):
     assert relerr(host(prob.jacobian_apply_pa(v, prec="mixed")), ora.jvp(inp["u"], inp["v"])) < 1e-5
     prob.pa_setup(u)
     assert relerr(host(prob.jacobian_apply_pa(v)), ora.jvp(inp["u"], inp["v"])) <= 1e-12
+
+
+DEGENERATE = [
+    Workload("one-elem-q3", 1, 1, 1, 3, 5, 4.0, 1e-3, 40, perturb=True, rho=True),  # one (curved-path) element
+    Workload("slab-q4", 1, 6, 2, 4, 6, 2.5, 1e-2, 41, rho=True),                     # one element thick
+    Workload("eps0-q2-curved", 3, 2, 4, 2, 3, 3.0, 0.0, 42, perturb=True),           # eps = 0 (p >= 2)
+]
+
+
+@pytest.mark.parametrize("w", DEGENERATE, ids=[w.name for w in DEGENERATE])
+def test_degenerate_meshes_match_oracle(w):
+    """Single element, single-element-thick slab and eps = 0: every operator
+    against the oracle, partial assembly bitwise equal to the fused apply."""
+    announce("degenerate", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    r_o, jv_o = ora.residual(inp["u"]), ora.jvp(inp["u"], inp["v"])
+    assert relerr(host(prob.residual(u)), r_o) <= 1e-12
+    jv = prob.jacobian_apply(u, v)
+    assert relerr(host(jv), jv_o) <= 1e-12
+    r2, jv2 = prob.residual_and_jvp(u, v)
+    assert relerr(host(r2), r_o) <= 1e-12 and relerr(host(jv2), jv_o) <= 1e-12
+    e_o = ora.energy(inp["u"])
+    assert abs(host(prob.energy(u))[0] - e_o) <= 1e-12 * abs(e_o)
+    lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, ora.N)
+    assert relerr(host(prob.grad_rho(u, dev(lam))), ora.grad_rho(inp["u"], lam)) <= 1e-12
+    assert relerr(host(prob.jacobian_apply(u, v, prec="mixed")), jv_o) <= 1e-4
+    prob.pa_setup(u)
+    assert torch.equal(prob.jacobian_apply_pa(v), jv)
+
+
+def test_all_dirichlet_mesh_gives_exact_zeros():
+    """One Q1 element: every node is a Dirichlet node, so the masked residual,
+    Jacobian action and design gradient are exactly zero, and both solvers
+    stop before their first step."""
+    w = Workload("all-dirichlet-q1", 1, 1, 1, 1, 2, 3.0, 1e-2, 43)
+    announce("all-dirichlet", w)
+    prob, ora, inp = setup(w)
+    assert ora.mask.sum() == 0
+    u, v = dev(inp["u"]), dev(inp["v"])
+    assert not host(prob.residual(u)).any()
+    assert not host(prob.jacobian_apply(u, v)).any()
+    e_o = ora.energy(inp["u"])
+    assert abs(host(prob.energy(u))[0] - e_o) <= 1e-12 * abs(e_o)
+    us, rep = prob.newton_solve(rtol=1e-10)
+    assert rep["status"] == 0 and rep["newton_iters"] == 0 and rep["cg_iters_total"] == 0
+    assert not host(us).any()
+    grad, lam, rep = prob.adjoint_gradient(us, dev(ora.b))
+    assert rep["status"] == 0 and rep["cg_iters_total"] == 0
+    assert not host(lam).any() and not host(grad).any()
