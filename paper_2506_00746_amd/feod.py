@@ -244,6 +244,10 @@ class Problem:
                self._ctx)
         return out
 
+    def jvp(self, u, v, out=None, prec="fp64"):
+        """J(u) v (the same call as ``jacobian_apply``)."""
+        return self.jacobian_apply(u, v, out=out, prec=prec)
+
     def residual_and_jvp(self, u, v, prec="fp64"):
         r = self._vec()
         jv = self.jacobian_apply(u, v, residual_out=r, prec=prec)
@@ -323,6 +327,10 @@ class Problem:
         st = lib().feod_newton_solve(self._ctx, self._ptr(u, self.n_dofs, "u"), ctypes.byref(o), ctypes.byref(rep))
         _check(st, self._ctx)
         return u, rep.as_dict()
+
+    def newton(self, u0=None, **opts):
+        """The Newton-CG solve (the same call as ``newton_solve``)."""
+        return self.newton_solve(u0, **opts)
 
     def adjoint_gradient(self, u, g_u, **opts):
         o = default_opts(**opts)

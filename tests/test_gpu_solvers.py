@@ -132,9 +132,11 @@ def test_binding_argument_handling():
     announce("binding arguments", w)
     prob, ora, inp = setup(w)
     u, rep = prob.newton_solve(rtol=1e-12)
-    u2, rep2 = prob.newton_solve(u, rtol=1e-12)
+    u2, rep2 = prob.newton(u, rtol=1e-12)
     assert rep2["newton_iters"] == 0 and rep2["cg_iters_total"] == 0
     assert torch.equal(u, u2)
+    v = dev(inp["v"])
+    assert torch.equal(prob.jvp(u, v), prob.jacobian_apply(u, v))
     # float32 rho: the gradient comes back in rho's dtype and device
     b = dev(ora.b)
     rho64 = torch.as_tensor(inp["rho"], device="cuda:0").requires_grad_(True)
