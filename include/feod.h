@@ -254,7 +254,9 @@ feod_status feod_kernel_cost(const feod_ctx* ctx, int32_t op, feod_prec prec,
  * Tables: nodes[k+1], qpts[nq], qwts[nq], Bhat[nq*(k+1)], Dhat[nq*(k+1)]
  * (row q, column a).  Maps: emap[E*(k+1)^3] (global DOF or -1 on Dirichlet
  * DOFs), toff[N+1] and tidx[toff[N]] (E-vector positions e*(k+1)^3 + local
- * node of the entries summed into each DOF, by ascending element).  load: b (N, unmasked). Any pointer may be NULL. */
+ * node of the entries summed into each DOF, by ascending element); any
+ * pointer of these two may be NULL.  load: b (N doubles, unmasked), not NULL
+ * (FEOD_EINVAL). */
 feod_status feod_host_tables(const feod_ctx* ctx, double* nodes, double* qpts,
                              double* qwts, double* Bhat, double* Dhat);
 feod_status feod_host_maps(const feod_ctx* ctx, int32_t* emap, int32_t* toff,
