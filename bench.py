@@ -223,6 +223,14 @@ def tangent_rows(feod, WORKLOADS, make_inputs, dev, args):
                      "ns_per_element": ms * 1e6 / w.n_elems,
                      "TFLOP/s": flops / (ms * 1e-3) / 1e12, "frac_fp64_peak": flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFS,
                      "GB/s": bytes_ / (ms * 1e-3) / 1e9, "matrix_entries": Ke.numel()}
+        # the paper's ELM variant (Table 1): forward AD through the element
+        # residual, one Jacobian action per local DOF; FLOPs from the cost model
+        ms_elm = timed_loop(lambda: pb.element_tangents(u, out=Ke, method="elm"), max(3, args.steps // 10), 2)
+        f_elm = pb.kernel_cost("elm")[1]
+        out[name]["elm"] = {"ms_per_launch": ms_elm, "ns_per_element": ms_elm * 1e6 / w.n_elems,
+                            "TFLOP/s": f_elm / (ms_elm * 1e-3) / 1e12,
+                            "frac_fp64_peak": f_elm / (ms_elm * 1e-3) / 1e12 / FP64_PEAK_TFS,
+                            "time_vs_quadrature_point_ad": ms_elm / ms}
         log(f"[bench] element tangents {name}: {out[name]}")
         del pb, u, Ke
         torch.cuda.empty_cache()

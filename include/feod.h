@@ -183,6 +183,16 @@ feod_status feod_element_vectors(feod_ctx* ctx, int32_t op, const double* u, con
 feod_status feod_element_tangents(feod_ctx* ctx, const double* u, int64_t first, int64_t count,
                                   double* Ke);
 
+/* The same matrices by element-level forward AD, the paper's ELM variant of
+ * Table 1 (AD through the whole element residual r_e = B^T D(B u_e) of Eq. 3
+ * instead of at the quadrature points): column j of K_e is one element
+ * Jacobian action B^T J_D B e_j with the unit vector e_j of local node j as
+ * the dual direction, so an element costs (k+1)^3 passes of B, D and B^T
+ * where feod_element_tangents contracts B^T J_D B once.  Same arguments,
+ * layout and errors as feod_element_tangents; for comparing the two. */
+feod_status feod_element_tangents_elm(feod_ctx* ctx, const double* u, int64_t first, int64_t count,
+                                      double* Ke);
+
 /* Partial assembly (the pointwise data of Fig. 1's caption): store the
  * gradients of M u at every quadrature point (3 per point, in the precision
  * of prec; physical gradients on affine meshes, reference ones on curved
@@ -243,7 +253,8 @@ feod_status feod_profile_read(feod_ctx* ctx, feod_kernel_stat* stats, int32_t ma
 
 /* Algorithmic cost of one launch of the fused element kernel for an
  * operation (0 residual, 1 Jacobian apply, 2 residual+Jacobian, 3 energy,
- * 4 gradient, 6 partial-assembly set-up, 7 partial-assembly Jacobian apply;
+ * 4 gradient, 6 partial-assembly set-up, 7 partial-assembly Jacobian apply,
+ * 8 element-level tangents (all (k+1)^3 directions, K_e written);
  * 5 (diagonal) is not modelled) at precision prec: bytes moved to/from HBM by the
  * design (unique reads of inputs and maps, E-vector writes) and floating
  * point operations (FMA = 2).  Host only. */

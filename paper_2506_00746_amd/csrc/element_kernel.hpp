@@ -243,12 +243,17 @@ __device__ __forceinline__ double wave_sum(const T* vals, int n, int lane) {
 }
 
 // Phase A for NF fields: gather lines (c,b) of the fields through the map and
-// contract in x.  Slot f of the x-pass buffer receives field src[f].
-template <int D1, int NQ, int EB, int NT, int XSTRIDE, int XQ, int NF, class T, class TB>
+// contract in x.  Slot f of the x-pass buffer receives field src[f].  UNIT:
+// the last field is not gathered but is the unit vector of local node
+// unit_j (a tangent direction of the element-level forward mode).  e0 is the
+// global index of the batch's first element.
+template <int D1, int NQ, int EB, int NT, int XSTRIDE, int XQ, int NF, class T, class TB, bool UNIT = false>
 __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const double* const (&src)[NF],
-                                        T* Xs, int e0, int n_valid, int tid, const int (*sE)[3]) {
+                                        T* Xs, int e0, int n_valid, int tid, const int (*sE)[3],
+                                        int unit_j = 0) {
   constexpr int Ne = D1 * D1 * D1;
   constexpr int XS = D1 * NQ * XQ;
+  constexpr int NG = UNIT ? NF - 1 : NF;  // gathered fields
   for (int l = tid; l < EB * D1 * D1; l += NT) {
 #if FEOD_EVEC_ROWMAJOR
     const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: consecutive elements of the row
@@ -263,7 +268,7 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
       for (int a = 0; a < D1; ++a) {
         const int idx = m[a];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) in[f][a] = idx >= 0 ? (T)src[f][idx] : T(0);
+        for (int f = 0; f < NG; ++f) in[f][a] = idx >= 0 ? (T)src[f][idx] : T(0);
       }
     } else if (el < n_valid) {
       // the same map computed from the lattice: node (k ex + a, k ey + b, k ez + c),
@@ -277,16 +282,20 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
       for (int a = 0; a < D1; ++a) {
         const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) {
+        for (int f = 0; f < NG; ++f) {
           const double val = src[f][base + a];
           in[f][a] = ok ? (T)val : T(0);
         }
       }
     } else {
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
+      for (int f = 0; f < NG; ++f)
 #pragma unroll
         for (int a = 0; a < D1; ++a) in[f][a] = 0;
+    }
+    if constexpr (UNIT) {
+#pragma unroll
+      for (int a = 0; a < D1; ++a) in[NF - 1][a] = cb * D1 + a == unit_j ? T(1) : T(0);
     }
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
@@ -426,7 +435,10 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   constexpr int Ne = D1 * D1 * D1;
   constexpr int NQ2 = NQ * NQ;
   constexpr bool PA = OP == OP_JVP_PA, QSTORE = OP == OP_QSTORE;
-  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD || PA) ? 2 : 1;  // register fields
+  // element-level forward AD: one tangent column of K_e per blockIdx.y, the
+  // direction being the unit vector of that local node (no gather)
+  constexpr bool ELM = OP == OP_ELM;
+  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD || PA || ELM) ? 2 : 1;  // register fields
   constexpr int O = (OP == OP_RESJVP) ? 2 : 1;                                    // output fields
   constexpr bool REDUCE = (OP == OP_ENERGY || OP == OP_GRAD);
   constexpr bool SEQ = C::SEQ && F == 2 && !PA;
@@ -448,11 +460,12 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   T* Vs = smem + EB * L::region;    // [el][24] vertex coordinates
 
   const int tid = threadIdx.x;
-  const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EB;
+  const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EB;  // batch start, relative to eoff
+  const int eoff = ELM ? P.e_first : 0;                   // global index of element 0
   const int n_valid = min(EB, P.E - e0);
   __shared__ int sE[EB][3];  // (ex, ey, ez) of each element of the batch
   if (tid < EB) {
-    const uint32_t e = (uint32_t)(e0 + tid), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
+    const uint32_t e = (uint32_t)(eoff + e0 + tid), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
     sE[tid][0] = (int)(e - t * (uint32_t)P.nx);
     sE[tid][1] = (int)(t - z * (uint32_t)P.ny);
     sE[tid][2] = (int)z;
@@ -472,7 +485,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       const int el = i / 24, r = i - el * 24, vtx = r / 3, al = r - vtx * 3;
       T val = 0;
       if (el < n_valid) {
-        const uint32_t e = (uint32_t)(e0 + el), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
+        const uint32_t e = (uint32_t)(eoff + e0 + el), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
         const int ex = (int)(e - t * (uint32_t)P.nx), ey = (int)(t - z * (uint32_t)P.ny), ez = (int)z;
         const int gi = (ex + (vtx & 1)) + (P.nx + 1) * ((ey + ((vtx >> 1) & 1)) + (P.ny + 1) * (ez + (vtx >> 2)));
         val = (T)P.verts[(int64_t)gi * 3 + al];
@@ -487,6 +500,10 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   if constexpr (PA) {
     const double* const src[1] = {P.v};
     phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+  } else if constexpr (ELM) {
+    const double* const src[2] = {P.u, P.u};  // the second field is the unit direction
+    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 2, T, Tab<D1, NQ, T>, true>(tb, P, src, Xs, eoff + e0, n_valid, tid, sE,
+                                                                       (int)blockIdx.y);
   } else if constexpr (F == 2 && !SEQ) {
     const double* const src[2] = {P.u, P.v};
     phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
@@ -556,7 +573,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   if (L::ALIAS) __syncthreads();  // x-pass buffer consumed: the z-back may overwrite it
   if (active && !QSTORE) {
     const bool valid = el < n_valid;
-    const T rho = (P.rho != nullptr && valid) ? (T)P.rho[e0 + el] : T(1);
+    const T rho = (P.rho != nullptr && valid) ? (T)P.rho[eoff + e0 + el] : T(1);
     const T wxy = sW[qx] * sW[qy];
     // geometry: affine -> constant diagonal; curved -> Jg = J0 + xi_z J1 (column 2 constant)
     T J0[3][3], J1[3][2];
@@ -661,7 +678,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
         cd[5][qz] = Ch[1][2] + Ch[2][1];
       } else if constexpr (OP == OP_RESIDUAL) {
         flux<PK, T, T>(gu, eps2, r, Fo[0]);
-      } else if constexpr (OP == OP_JVP || OP == OP_RESJVP || PA) {
+      } else if constexpr (OP == OP_JVP || OP == OP_RESJVP || PA || ELM) {
         dual<T> gd[3], Fd[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) gd[a] = {gu[a], gv[a]};
@@ -866,14 +883,17 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
     const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: adjacent E-vector stretches
     const int c = cb / D1, b = cb - c * D1;
     if (el >= n_valid) continue;
-    const int64_t pos = ((((int64_t)sE[el][2] * P.ny + sE[el][1]) * D1 + c) * D1 + b) * P.nx * D1 +
-                        (int64_t)sE[el][0] * D1;
+    const int64_t pos = ELM ? ((int64_t)(e0 + el) * Ne + cb * D1) * Ne + blockIdx.y  // column of K_e
+                            : ((((int64_t)sE[el][2] * P.ny + sE[el][1]) * D1 + c) * D1 + b) * P.nx * D1 +
+                                  (int64_t)sE[el][0] * D1;
 #else
     const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
     const int c = cb / D1, b = cb - c * D1;
     if (el >= n_valid) continue;
-    const int64_t pos = (int64_t)(e0 + el) * Ne + cb * D1;
+    const int64_t pos = ELM ? ((int64_t)(e0 + el) * Ne + cb * D1) * Ne + blockIdx.y  // column of K_e
+                            : (int64_t)(e0 + el) * Ne + cb * D1;
 #endif
+    constexpr int OSTR = ELM ? Ne : 1;  // output stride along a (a K_e column for ELM)
     if constexpr (DIAG) {
       const T* k = Xs + el * L::XSTR + c * L::XC + b;
       T kd2[NQ], kb2[NQ], kdb[NQ];
@@ -919,7 +939,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
             s += tb.Dx[qx * D1 + a] * k0[qx];
             s += tb.B[qx * D1 + a] * k1[qx];
           }
-          out[a] = s;
+          out[a * OSTR] = s;
         }
         continue;
       }
@@ -936,7 +956,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       eo_backward_add<D1, NQ, true>(tb.Pb, tb.Nb, xe, xo, xm, sp, sm);
       eo_backward_finish<D1, NQ>(sp, sm, y);
 #pragma unroll
-      for (int a = 0; a < D1; ++a) out[a] = y[a];
+      for (int a = 0; a < D1; ++a) out[a * OSTR] = y[a];
     }
   }
 }
@@ -988,8 +1008,8 @@ inline void no_tangents(ElemLaunchers&) {}
     const int blocks = (P.E + EB - 1) / EB;                                                       \
     if (blocks == 0) return hipSuccess;                                                           \
     const Tab<DD, QQ, T> tb = make_tab<DD, QQ, T>(P.htab, CURVED ? nullptr : P.hinv);             \
-    hipLaunchKernelGGL((element_kernel<DD, QQ, T, OP, CURVED, PK>), dim3(blocks), dim3(NT), 0, s, \
-                       P, tb);                                                                    \
+    const dim3 grid(blocks, OP == OP_ELM ? DD * DD * DD : 1);                                    \
+    hipLaunchKernelGGL((element_kernel<DD, QQ, T, OP, CURVED, PK>), grid, dim3(NT), 0, s, P, tb);  \
     return hipGetLastError();                                                                     \
   }                                                                                               \
   template <class T, bool CURVED, int PK>                                                         \
@@ -1002,6 +1022,8 @@ inline void no_tangents(ElemLaunchers&) {}
     t.op[OP_DIAG][CURVED][PK] = &launch_##DD##_##QQ<T, OP_DIAG, CURVED, PK>;                      \
     t.op[OP_QSTORE][CURVED][PK] = &launch_##DD##_##QQ<T, OP_QSTORE, CURVED, PK>;                  \
     t.op[OP_JVP_PA][CURVED][PK] = &launch_##DD##_##QQ<T, OP_JVP_PA, CURVED, PK>;                  \
+    if constexpr (sizeof(T) == 8 && DD <= 5)                                                      \
+      t.op[OP_ELM][CURVED][PK] = &launch_##DD##_##QQ<T, OP_ELM, CURVED, PK>;                      \
   }                                                                                               \
   template <class T, bool CURVED>                                                                 \
   static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                       \

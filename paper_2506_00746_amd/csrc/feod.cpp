@@ -247,10 +247,10 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
 const char* op_name(int op, int prec) {
   static const char* n64[] = {"element_residual_f64", "element_jvp_f64", "element_resjvp_f64",
                               "element_energy_f64", "element_grad_f64", "element_diag_f64",
-                              "element_qstore_f64", "element_jvp_pa_f64"};
+                              "element_qstore_f64", "element_jvp_pa_f64", "element_elm_f64"};
   static const char* n32[] = {"element_residual_f32", "element_jvp_f32", "element_resjvp_f32",
                               "element_energy_f32", "element_grad_f32", "element_diag_f32",
-                              "element_qstore_f32", "element_jvp_pa_f32"};
+                              "element_qstore_f32", "element_jvp_pa_f32", "element_elm_f32"};
   return prec ? n32[op] : n64[op];
 }
 
@@ -697,6 +697,23 @@ feod_status feod_element_tangents(feod_ctx* c, const double* u, int64_t first, i
   return timed(c, "element_tangent_f64", [&] { return fn(P, c->stream); });
 }
 
+feod_status feod_element_tangents_elm(feod_ctx* c, const double* u, int64_t first, int64_t count, double* Ke) {
+  TRY(need_bound(c));
+  TRY(check_vec(c, u, "u"));
+  TRY(check_vec(c, Ke, "Ke"));
+  if (first < 0 || count < 0 || first + count > c->lat.E)
+    return fail(c, FEOD_EINVAL, "element range outside the mesh");
+  if (count > INT32_MAX) return fail(c, FEOD_EINVAL, "too many elements in one call");
+  ElemLaunch fn = c->L->prec[0].op[OP_ELM][c->curved ? 1 : 0][pow_kind(c->p)];
+  if (!fn) return fail(c, FEOD_EUNSUPPORTED, "element-level tangents are built for k <= 4 only");
+  if (overlap(u, (size_t)c->lat.N * 8, Ke, (size_t)count * c->Ne * c->Ne * 8))
+    return fail(c, FEOD_EINVAL, "Ke overlaps u");
+  ElemParams P = params(c, u, nullptr, Ke, nullptr, 0);
+  P.e_first = (int32_t)first;
+  P.E = (int32_t)count;
+  return timed(c, "element_elm_f64", [&] { return fn(P, c->stream); });
+}
+
 feod_status feod_pa_setup(feod_ctx* c, const double* u, feod_prec prec) {
   TRY(need_bound(c));
   TRY(check_prec(c, prec));
@@ -995,14 +1012,15 @@ static double pointwise_flops(int op, int pk, bool curved) {
     case OP_ENERGY: f = 1 + 6 + 2 + 4 + apow_s[pk]; break;  // W = a a^r / p, accumulate rho w det W
     case OP_GRAD: f = 1 + 6 + 5 + 4 + apow_s[pk]; break;    // a^r g_u . g_lambda, accumulate
     case OP_JVP_PA: f = 2 + 17 + 9 + apow_d[pk]; break;
+    case OP_ELM: f = 2 + 17 + 9 + apow_d[pk]; break;  // one Jacobian action per direction
     default: f = 0;
   }
   // affine: the derivative tables carry 1/h; per point only sd = s det and
   // the output scaling sd F (per output field)
-  const double affine[OP_COUNT] = {4, 4, 7, 0, 0, 0, 0, 4};
+  const double affine[OP_COUNT] = {4, 4, 7, 0, 0, 0, 0, 4, 4};
   // curved: Jg (12), adjugate (27), det (5), 1/det (1), physical gradient per
   // input field (18 each), reference flux s adj F per output field (18 each)
-  const double geo[OP_COUNT] = {81, 99, 117, 63, 81, 0, 0, 99};
+  const double geo[OP_COUNT] = {81, 99, 117, 63, 81, 0, 0, 99, 99};
   return f + (curved ? geo[op] : affine[op]);
 }
 
@@ -1014,10 +1032,12 @@ feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, doub
   const double ts = prec == FEOD_MIXED ? 4.0 : 8.0;
   // one sum-factorised gradient pass (B or B^T) per field, FMA = 2
   const double S = 4 * nq * D1 * D1 * D1 + 6 * nq * nq * D1 * D1 + 6 * nq * nq * nq * D1;
-  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0, 1, 2};
-  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1, 1, 1};
-  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1, 0, 1};
-  *flops = E * (passes[op] * S + NQ3 * pointwise_flops(op, pow_kind(c->p), c->curved));
+  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0, 1, 2, 3};
+  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1, 1, 1, 1};
+  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1, 0, 1, 0};
+  // element-level AD (op 8): one Jacobian action per tangent direction, Ne of them
+  const double dirs = op == OP_ELM ? Ne : 1.0;
+  *flops = E * dirs * (passes[op] * S + NQ3 * pointwise_flops(op, pow_kind(c->p), c->curved));
   double b = fields[op] * 8.0 * N;  // unique L-vector reads
   if (c->explicit_maps) b += 4.0 * E * Ne;  // stored element-to-DOF map
   if (c->has_rho) b += 8.0 * E;
@@ -1025,6 +1045,7 @@ feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, doub
   b += outs[op] * ts * E * Ne;
   if (op == OP_ENERGY || op == OP_GRAD) b += 8.0 * E;
   if (op == OP_QSTORE || op == OP_JVP_PA) b += 3.0 * NQ3 * E * ts;  // stored gradients
+  if (op == OP_ELM) b += 8.0 * E * Ne * Ne;                            // the K_e written
   *bytes = b;
   return FEOD_OK;
 }

@@ -17,7 +17,8 @@ enum : int {
   OP_DIAG = 5,      // E-vector of diag(J)
   OP_QSTORE = 6,    // partial assembly: reference gradients of M u at every point -> qdata
   OP_JVP_PA = 7,    // Jacobian action with the stored gradients (v gathered only)
-  OP_COUNT = 8
+  OP_ELM = 8,       // element tangent column by element-level forward AD (FP64, D1 <= 5)
+  OP_COUNT = 9
 };
 
 // Arguments of the fused element kernel (passed by value).
@@ -53,7 +54,7 @@ struct ElemParams {
                           // physical on affine meshes, reference on curved ones)
   const double* htab;     // host copy of the FP64 tables (B, D, w, xi); read by the launcher
   int32_t E, nx, ny, nz;
-  int32_t e_first;        // first element (element-tangent kernel; E is then the count)
+  int32_t e_first;        // first element (element-tangent kernels; E is then the count)
   int32_t k, Lx, Ly, Lz;  // order and node-lattice extents (k n + 1 per direction)
   double hinv[3];         // affine meshes: 1/h per direction
   double det;             // affine meshes: element volume h_x h_y h_z

@@ -22,7 +22,8 @@ FEOD_OK, FEOD_EINVAL, FEOD_EUNSUPPORTED, FEOD_EHIP, FEOD_ENOCONV, FEOD_ENONFINIT
 STATUS_NAMES = {0: "FEOD_OK", 1: "FEOD_EINVAL", 2: "FEOD_EUNSUPPORTED", 3: "FEOD_EHIP",
                 4: "FEOD_ENOCONV", 5: "FEOD_ENONFINITE", 6: "FEOD_EBREAKDOWN", 7: "FEOD_ESTATE"}
 PREC = {"fp64": 0, "mixed": 1}
-OPS = {"residual": 0, "jvp": 1, "resjvp": 2, "energy": 3, "grad": 4, "diag": 5, "pa_setup": 6, "jvp_pa": 7}
+OPS = {"residual": 0, "jvp": 1, "resjvp": 2, "energy": 3, "grad": 4, "diag": 5, "pa_setup": 6, "jvp_pa": 7,
+       "elm": 8}
 
 
 class FeodError(RuntimeError):
@@ -80,6 +81,7 @@ _SIGS = {
     "feod_pa_setup": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "feod_jacobian_apply_pa": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_element_tangents": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
+    "feod_element_tangents_elm": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
     "feod_element_vectors": (ctypes.c_int, [_P, ctypes.c_int32, _P, _P, ctypes.c_int]),
     "feod_jacobian_diagonal": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_newton_solve": (ctypes.c_int, [_P, _P, _P, _P]),
@@ -260,16 +262,19 @@ class Problem:
         _check(lib().feod_element_vectors(self._ctx, {"residual": 0, "jvp": 1, "resjvp": 2}[op],
                                           self._ptr(u, self.n_dofs, "u"), vp, PREC[prec]), self._ctx)
 
-    def element_tangents(self, u, first=0, count=None, out=None):
-        """K_e (Eq. 3) for elements first..first+count-1: (count, Ne, Ne) FP64."""
+    def element_tangents(self, u, first=0, count=None, out=None, method="res"):
+        """K_e (Eq. 3) for elements first..first+count-1: (count, Ne, Ne) FP64.
+        method "res": AD at the quadrature points, B^T J_D B contracted once;
+        "elm": element-level forward AD, one Jacobian action per local DOF
+        (the paper's ELM variant, for comparison)."""
         count = self.n_elems - first if count is None else count
         ne = (self.k + 1) ** 3
         if out is None:
             out = torch.empty((count, ne, ne), dtype=torch.float64, device=self.device)
         op = self._ptr(out, count * ne * ne, "out")
+        fn = {"res": lib().feod_element_tangents, "elm": lib().feod_element_tangents_elm}[method]
         self._sync_stream()
-        _check(lib().feod_element_tangents(self._ctx, self._ptr(u, self.n_dofs, "u"), first, count, op),
-               self._ctx)
+        _check(fn(self._ctx, self._ptr(u, self.n_dofs, "u"), first, count, op), self._ctx)
         return out
 
     def pa_setup(self, u, prec="fp64"):

@@ -142,3 +142,8 @@ def test_cost_model_matches_its_formula():
         assert b == pytest.approx(nbytes, rel=1e-14), name
         b32, f32 = hs.cost[(op, "mixed")]
         assert f32 == f and b32 == pytest.approx(nbytes - 4.0 * e * d1 ** 3, rel=1e-14)
+        # element-level AD tangents: one Jacobian action per local DOF, u read
+        # once, K_e written
+        be, fe = hs.cost[("elm", "fp64")]
+        assert fe == pytest.approx(d1 ** 3 * flops, rel=1e-14), name
+        assert be == pytest.approx(nbytes - 8.0 * n - 8.0 * e * d1 ** 3 + 8.0 * e * d1 ** 6, rel=1e-14), name

@@ -192,6 +192,26 @@ def test_element_tangents_match_oracle(w):
             assert np.array_equal(part, Ke[2:2 + cnt])
 
 
+@pytest.mark.parametrize("w", [SMALL[0], SMALL[1], SMALL[2], SMALL[3], SMALL[4], SMALL[5], SMALL[7], SMALL[8]],
+                         ids=["c1", "q2-rho", "q2-curved", "q3-p4", "q3-curved", "q4", "q1-curved", "q2-generic"])
+def test_element_level_ad_tangents_match_oracle(w):
+    """The paper's ELM variant (forward AD through the whole element residual,
+    one Jacobian action per local DOF) gives the same K_e as the oracle and as
+    quadrature-point AD, on full meshes and on element sub-ranges."""
+    announce("element-level AD tangents", w)
+    prob, ora, inp = setup(w)
+    u = dev(inp["u"])
+    Kelm = host(prob.element_tangents(u, method="elm"))
+    assert relerr(Kelm, ora.element_tangents(inp["u"], np.arange(ora.E))) <= 1e-12
+    assert relerr(Kelm, host(prob.element_tangents(u))) <= 1e-13
+    part = host(prob.element_tangents(u, first=1, count=ora.E - 2, method="elm"))
+    assert np.array_equal(part, Kelm[1:-1])
+    for cnt in (1, 3, 5):
+        if 2 + cnt <= ora.E:
+            part = host(prob.element_tangents(u, first=2, count=cnt, method="elm"))
+            assert np.array_equal(part, Kelm[2:2 + cnt])
+
+
 def test_element_tangents_sampled_on_design_mesh():
     w = WORKLOADS["c4"]
     announce("element tangents c4 sampled")
@@ -209,6 +229,8 @@ def test_element_tangents_unsupported_order():
     prob, _, inp = setup(w, oracle=False)
     with pytest.raises(feod.FeodError, match="UNSUPPORTED"):
         prob.element_tangents(dev(inp["u"]))
+    with pytest.raises(feod.FeodError, match="UNSUPPORTED"):
+        prob.element_tangents(dev(inp["u"]), method="elm")
 
 
 @pytest.mark.parametrize("w", [SMALL[0], SMALL[2], SMALL[4], SMALL[6]], ids=["c1", "q2-curved", "q3-curved", "q7-curved"])
