@@ -73,6 +73,19 @@ def element_kernel_ms(prob, u, v, op, prec, steps, warmup):
     return timed_loop(lambda: prob.element_vectors(op, u, v, prec=prec), steps, warmup)
 
 
+def ad_overhead(prob, u, v, args):
+    """The FP64 Jacobian element kernel with J_D from dual numbers and with the
+    hand-coded J_D (the paper's Table 1 compares AD with hand-coded, HND);
+    the two timings are interleaved twice."""
+    d = h = 0.0
+    for _ in range(2):
+        d += element_kernel_ms(prob, u, v, "jvp", "fp64", args.steps, args.warmup)
+        prob.set_tangent_mode("hand")
+        h += element_kernel_ms(prob, u, v, "jvp", "fp64", args.steps, args.warmup)
+        prob.set_tangent_mode("dual")
+    return {"dual_us": d / 2 * 1e3, "hand_us": h / 2 * 1e3, "dual_vs_hand": d / h}
+
+
 def stored_traffic(workload, kernel):
     """HBM bytes per launch from the committed rocprofv3 summary, if it was
     measured on the current kernel sources (else None)."""
@@ -413,6 +426,7 @@ def main():
         rows[w.name].update(apply_rows(prob, u, v, w, args,
                                        only=("jvp_mixed", "residual_fp64", "residual_jvp_fp64")))
         rows[w.name]["jvp_mixed"]["speedup_vs_fp64_apply"] = rows[w.name]["jvp_mixed"]["GDOF/s"] / value
+        rows[w.name]["ad_overhead"] = ad_overhead(prob, u, v, args)
         log(f"[bench] {w.name} rows: {rows[w.name]}")
         del prob, u, v, jv
         torch.cuda.empty_cache()
@@ -425,6 +439,8 @@ def main():
             vv = torch.as_tensor(ii["v"], device=dev)
             rows[name] = apply_rows(pb, uu, vv, wl, args, only=("jvp_fp64", "jvp_mixed", "residual_fp64"))
             log(f"[bench] {name}: { {k: (x['GDOF/s'], x['kernel_us'], x['kernel_frac']) for k, x in rows[name].items()} }")
+            rows[name]["ad_overhead"] = ad_overhead(pb, uu, vv, args)
+            log(f"[bench] {name} AD vs hand-coded J_D: {rows[name]['ad_overhead']}")
             del pb, uu, vv
             torch.cuda.empty_cache()
         rows["solves"] = solve_rows(feod, WORKLOADS, make_inputs, dev)

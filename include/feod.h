@@ -154,6 +154,17 @@ feod_status feod_sizes(const feod_ctx* ctx, int64_t* n_dofs, int64_t* n_elems);
 enum { FEOD_MAPS_LATTICE = 0, FEOD_MAPS_EXPLICIT = 1 };
 feod_status feod_set_map_mode(feod_ctx* ctx, int32_t mode);
 
+/* How the FP64 Jacobian actions obtain J_D at the quadrature points (paper:
+ * Table 1 compares AD with a hand-coded implementation, HND).
+ * FEOD_TANGENT_DUAL (default): forward-mode dual numbers through the flux
+ * (the remark after Eq. (2)).  FEOD_TANGENT_HAND: the same tangent written out
+ * by hand, dF = a^r dg + (p-2) a^(r-1) (g . dg) g, for measuring the cost of
+ * the dual numbers.  Affects the FP64 Jacobian action of feod_jacobian_apply
+ * (without residual), feod_element_vectors op 1 and the fused applies of the
+ * solvers; results agree to rounding. */
+enum { FEOD_TANGENT_DUAL = 0, FEOD_TANGENT_HAND = 1 };
+feod_status feod_set_tangent_mode(feod_ctx* ctx, int32_t mode);
+
 /* Change the stream later calls enqueue on. */
 feod_status feod_set_stream(feod_ctx* ctx, void* stream);
 
@@ -254,7 +265,8 @@ feod_status feod_profile_read(feod_ctx* ctx, feod_kernel_stat* stats, int32_t ma
 /* Algorithmic cost of one launch of the fused element kernel for an
  * operation (0 residual, 1 Jacobian apply, 2 residual+Jacobian, 3 energy,
  * 4 gradient, 6 partial-assembly set-up, 7 partial-assembly Jacobian apply,
- * 8 element-level tangents (all (k+1)^3 directions, K_e written);
+ * 8 element-level tangents (all (k+1)^3 directions, K_e written), 9 the
+ * Jacobian apply with the hand-coded J_D (counted as op 1);
  * 5 (diagonal) is not modelled) at precision prec: bytes moved to/from HBM by the
  * design (unique reads of inputs and maps, E-vector writes) and floating
  * point operations (FMA = 2).  Host only. */

@@ -438,7 +438,8 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   // element-level forward AD: one tangent column of K_e per blockIdx.y, the
   // direction being the unit vector of that local node (no gather)
   constexpr bool ELM = OP == OP_ELM;
-  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD || PA || ELM) ? 2 : 1;  // register fields
+  constexpr bool HND = OP == OP_JVP_HND;  // Jacobian action, hand-coded J_D
+  constexpr int F = (OP == OP_JVP || OP == OP_RESJVP || OP == OP_GRAD || PA || ELM || HND) ? 2 : 1;  // register fields
   constexpr int O = (OP == OP_RESJVP) ? 2 : 1;                                    // output fields
   constexpr bool REDUCE = (OP == OP_ENERGY || OP == OP_GRAD);
   constexpr bool SEQ = C::SEQ && F == 2 && !PA;
@@ -678,6 +679,8 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
         cd[5][qz] = Ch[1][2] + Ch[2][1];
       } else if constexpr (OP == OP_RESIDUAL) {
         flux<PK, T, T>(gu, eps2, r, Fo[0]);
+      } else if constexpr (HND) {
+        flux_tangent_hand<PK, T>(gu, gv, eps2, r, Fo[0]);
       } else if constexpr (OP == OP_JVP || OP == OP_RESJVP || PA || ELM) {
         dual<T> gd[3], Fd[3];
 #pragma unroll
@@ -1024,6 +1027,8 @@ inline void no_tangents(ElemLaunchers&) {}
     t.op[OP_JVP_PA][CURVED][PK] = &launch_##DD##_##QQ<T, OP_JVP_PA, CURVED, PK>;                  \
     if constexpr (sizeof(T) == 8 && DD <= 5)                                                      \
       t.op[OP_ELM][CURVED][PK] = &launch_##DD##_##QQ<T, OP_ELM, CURVED, PK>;                      \
+    if constexpr (sizeof(T) == 8)                                                                 \
+      t.op[OP_JVP_HND][CURVED][PK] = &launch_##DD##_##QQ<T, OP_JVP_HND, CURVED, PK>;              \
   }                                                                                               \
   template <class T, bool CURVED>                                                                 \
   static void fill_##DD##_##QQ(ElemLaunchers::PerPrec& t) {                                       \

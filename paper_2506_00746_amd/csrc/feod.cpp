@@ -49,6 +49,7 @@ struct feod_ctx {
   std::vector<double> htab;  // B, D, w, xi concatenated (kernel argument source)
   bool has_rho = false;
   bool explicit_maps = false;  // G / G^T from stored maps (true) or computed from the lattice
+  bool hand_tangent = false;   // FP64 Jacobian actions with the hand-coded J_D (comparison)
   // workspace
   char* ws = nullptr;
   size_t ws_bytes = 0;
@@ -247,14 +248,17 @@ ElemParams params(feod_ctx* c, const double* u, const double* v, void* out0, voi
 const char* op_name(int op, int prec) {
   static const char* n64[] = {"element_residual_f64", "element_jvp_f64", "element_resjvp_f64",
                               "element_energy_f64", "element_grad_f64", "element_diag_f64",
-                              "element_qstore_f64", "element_jvp_pa_f64", "element_elm_f64"};
+                              "element_qstore_f64", "element_jvp_pa_f64", "element_elm_f64",
+                              "element_jvp_hand_f64"};
   static const char* n32[] = {"element_residual_f32", "element_jvp_f32", "element_resjvp_f32",
                               "element_energy_f32", "element_grad_f32", "element_diag_f32",
-                              "element_qstore_f32", "element_jvp_pa_f32", "element_elm_f32"};
+                              "element_qstore_f32", "element_jvp_pa_f32", "element_elm_f32",
+                              "element_jvp_hand_f32"};
   return prec ? n32[op] : n64[op];
 }
 
 feod_status run_element(feod_ctx* c, int op, int prec, const ElemParams& P) {
+  if (op == OP_JVP && prec == 0 && c->hand_tangent) op = OP_JVP_HND;
   ElemLaunch fn = c->L->prec[prec].op[op][c->curved ? 1 : 0][P.powkind];
   if (!fn) return fail(c, FEOD_EUNSUPPORTED, "operation not built for this (k, nq)");
   return timed(c, op_name(op, prec), [&] { return fn(P, c->stream); });
@@ -630,6 +634,13 @@ feod_status feod_set_map_mode(feod_ctx* c, int32_t mode) {
   if (!c) return fail(nullptr, FEOD_EINVAL, "null context");
   if (mode != FEOD_MAPS_LATTICE && mode != FEOD_MAPS_EXPLICIT) return fail(c, FEOD_EINVAL, "invalid map mode");
   c->explicit_maps = mode == FEOD_MAPS_EXPLICIT;
+  return FEOD_OK;
+}
+
+feod_status feod_set_tangent_mode(feod_ctx* c, int32_t mode) {
+  if (!c) return fail(nullptr, FEOD_EINVAL, "null context");
+  if (mode != FEOD_TANGENT_DUAL && mode != FEOD_TANGENT_HAND) return fail(c, FEOD_EINVAL, "invalid tangent mode");
+  c->hand_tangent = mode == FEOD_TANGENT_HAND;
   return FEOD_OK;
 }
 
@@ -1013,14 +1024,15 @@ static double pointwise_flops(int op, int pk, bool curved) {
     case OP_GRAD: f = 1 + 6 + 5 + 4 + apow_s[pk]; break;    // a^r g_u . g_lambda, accumulate
     case OP_JVP_PA: f = 2 + 17 + 9 + apow_d[pk]; break;
     case OP_ELM: f = 2 + 17 + 9 + apow_d[pk]; break;  // one Jacobian action per direction
+    case OP_JVP_HND: f = 2 + 17 + 9 + apow_d[pk]; break;  // the same count as the dual version
     default: f = 0;
   }
   // affine: the derivative tables carry 1/h; per point only sd = s det and
   // the output scaling sd F (per output field)
-  const double affine[OP_COUNT] = {4, 4, 7, 0, 0, 0, 0, 4, 4};
+  const double affine[OP_COUNT] = {4, 4, 7, 0, 0, 0, 0, 4, 4, 4};
   // curved: Jg (12), adjugate (27), det (5), 1/det (1), physical gradient per
   // input field (18 each), reference flux s adj F per output field (18 each)
-  const double geo[OP_COUNT] = {81, 99, 117, 63, 81, 0, 0, 99, 99};
+  const double geo[OP_COUNT] = {81, 99, 117, 63, 81, 0, 0, 99, 99, 99};
   return f + (curved ? geo[op] : affine[op]);
 }
 
@@ -1032,9 +1044,9 @@ feod_status feod_kernel_cost(const feod_ctx* c, int32_t op, feod_prec prec, doub
   const double ts = prec == FEOD_MIXED ? 4.0 : 8.0;
   // one sum-factorised gradient pass (B or B^T) per field, FMA = 2
   const double S = 4 * nq * D1 * D1 * D1 + 6 * nq * nq * D1 * D1 + 6 * nq * nq * nq * D1;
-  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0, 1, 2, 3};
-  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1, 1, 1, 1};
-  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1, 0, 1, 0};
+  const double passes[OP_COUNT] = {2, 3, 4, 1, 2, 0, 1, 2, 3, 3};
+  const double fields[OP_COUNT] = {1, 2, 2, 1, 2, 1, 1, 1, 1, 2};
+  const double outs[OP_COUNT] = {1, 1, 2, 0, 0, 1, 0, 1, 0, 1};
   // element-level AD (op 8): one Jacobian action per tangent direction, Ne of them
   const double dirs = op == OP_ELM ? Ne : 1.0;
   *flops = E * dirs * (passes[op] * S + NQ3 * pointwise_flops(op, pow_kind(c->p), c->curved));

@@ -18,7 +18,8 @@ enum : int {
   OP_QSTORE = 6,    // partial assembly: reference gradients of M u at every point -> qdata
   OP_JVP_PA = 7,    // Jacobian action with the stored gradients (v gathered only)
   OP_ELM = 8,       // element tangent column by element-level forward AD (FP64, D1 <= 5)
-  OP_COUNT = 9
+  OP_JVP_HND = 9,   // Jacobian action with the hand-coded J_D instead of dual numbers (FP64)
+  OP_COUNT = 10
 };
 
 // Arguments of the fused element kernel (passed by value).

@@ -23,7 +23,7 @@ STATUS_NAMES = {0: "FEOD_OK", 1: "FEOD_EINVAL", 2: "FEOD_EUNSUPPORTED", 3: "FEOD
                 4: "FEOD_ENOCONV", 5: "FEOD_ENONFINITE", 6: "FEOD_EBREAKDOWN", 7: "FEOD_ESTATE"}
 PREC = {"fp64": 0, "mixed": 1}
 OPS = {"residual": 0, "jvp": 1, "resjvp": 2, "energy": 3, "grad": 4, "diag": 5, "pa_setup": 6, "jvp_pa": 7,
-       "elm": 8}
+       "elm": 8, "jvp_hand": 9}
 
 
 class FeodError(RuntimeError):
@@ -75,6 +75,7 @@ _SIGS = {
     "feod_sizes": (ctypes.c_int, [_P, _P, _P]),
     "feod_set_stream": (ctypes.c_int, [_P, _P]),
     "feod_set_map_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "feod_set_tangent_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P]),
@@ -226,6 +227,11 @@ class Problem:
     def set_map_mode(self, mode: str):
         """'lattice' (computed G/G^T, default) or 'explicit' (stored maps)."""
         _check(lib().feod_set_map_mode(self._ctx, {"lattice": 0, "explicit": 1}[mode]), self._ctx)
+
+    def set_tangent_mode(self, mode: str):
+        """'dual' (forward-mode dual numbers at the points, default) or 'hand'
+        (the hand-coded J_D, for comparison) for the FP64 Jacobian actions."""
+        _check(lib().feod_set_tangent_mode(self._ctx, {"dual": 0, "hand": 1}[mode]), self._ctx)
 
     # -- operators (Eq. (1), Eq. (2)) -------------------------------------
     def residual(self, u, out=None, prec="fp64"):

@@ -75,6 +75,22 @@ def test_mixed_precision_error_vs_fp64_oracle(w):
     assert e_r < 1e-4 and e_j < 1e-4 and e_g < 1e-4
 
 
+@pytest.mark.parametrize("w", SMALL, ids=IDS)
+def test_hand_coded_tangent_matches_dual_numbers(w):
+    """The hand-coded J_D (Table 1's HND) gives the oracle's Jacobian action,
+    and the dual-number one to rounding."""
+    announce("hand-coded tangent", w)
+    prob, ora, inp = setup(w)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    jv_dual = host(prob.jacobian_apply(u, v))
+    prob.set_tangent_mode("hand")
+    jv_hand = host(prob.jacobian_apply(u, v))
+    prob.set_tangent_mode("dual")
+    assert relerr(jv_hand, ora.jvp(inp["u"], inp["v"])) <= 1e-12
+    assert relerr(jv_hand, jv_dual) <= 1e-13
+    assert np.array_equal(host(prob.jacobian_apply(u, v)), jv_dual)
+
+
 def test_bitwise_determinism_and_symmetry():
     w = SMALL[2]
     announce("determinism", w)
