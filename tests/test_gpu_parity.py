@@ -148,6 +148,10 @@ def test_full_size_sampled_parity(name):
     rm = host(prob.jacobian_apply(u, v, prec="mixed"))
     print(f"[{name}] mixed JVP rel. error at sampled DOFs: "
           f"{relerr(rm[dofs], jv[dofs]):.2e}")
+    # the hand-coded J_D at full size: the dual-number apply to rounding
+    prob.set_tangent_mode("hand")
+    assert relerr(host(prob.jacobian_apply(u, v)), jv) <= 1e-13
+    prob.set_tangent_mode("dual")
     del prob
     torch.cuda.empty_cache()
 
@@ -237,6 +241,8 @@ def test_element_tangents_sampled_on_design_mesh():
         Ke = host(prob.element_tangents(dev(inp["u"]), first=int(first), count=16))
         Ko = ora.element_tangents(inp["u"], np.arange(first, first + 16))
         assert relerr(Ke, Ko) <= 1e-12
+        Kelm = host(prob.element_tangents(dev(inp["u"]), first=int(first), count=16, method="elm"))
+        assert relerr(Kelm, Ko) <= 1e-12
 
 
 def test_element_tangents_unsupported_order():
