@@ -16,8 +16,12 @@ back-to-back launches of the element stage alone on the library's stream,
 its HBM traffic from the committed rocprofv3 summary (when measured on the
 current kernel sources), and the CPU oracle timed on a bounded sample.
 
+Before the W warm-up steps the apply runs untimed for --settle seconds (0.5 by
+default): an idle GPU raises its clocks during the first milliseconds of work,
+and the K timed steps measure the steady state.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
-       [--no-extras] [--no-cpu-baseline] [--calibrate-copy]
+       [--settle S] [--no-extras] [--no-cpu-baseline] [--calibrate-copy]
 """
 from __future__ import annotations
 
@@ -38,6 +42,18 @@ FP32_PEAK_TFS = 78.6           # non-packed FP32 FMA: same lane rate as FP64
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def settle(fn, seconds):
+    """Run fn untimed, in synchronised rounds of 20, for at least `seconds` of
+    wall time: an idle GPU raises its clocks over the first milliseconds of
+    work, and the timed steps should see the steady state."""
+    import torch
+    t0 = time.time()
+    while time.time() - t0 < seconds:
+        for _ in range(20):
+            fn()
+        torch.cuda.synchronize()
 
 
 def timed_loop(fn, steps, warmup):
@@ -375,6 +391,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c2")
+    ap.add_argument("--settle", type=float, default=0.5,
+                    help="seconds of untimed applies before the warm-up steps (GPU clocks reach steady state)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -411,6 +429,7 @@ def main():
         prob.jacobian_apply(u, v, out=jv)
 
     log(f"[bench] {w.name}: N={N} E={w.n_elems} timed JVP fp64 x{args.steps}")
+    settle(jvp64, args.settle)
     ms = timed_loop(jvp64, args.steps, args.warmup)
     value = N / (ms * 1e-3) / 1e9
     stats = kernel_profile(prob, jvp64, min(args.steps, 50))
@@ -460,7 +479,7 @@ def main():
            "vs_baseline": None, "dtype": "f64", "data": "synthetic",
            "config": {"workload": f"{w.name}: {w.note}", "n_dofs": N, "n_elems": w.n_elems,
                       "order_k": w.k, "nq": w.nq, "p": w.p, "eps": w.eps, "seed": w.seed,
-                      "parallelism": "single GPU"},
+                      "parallelism": "single GPU", "settle_s": args.settle},
            "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
            "roofline_detail": roof, "cpu_baseline": cpu, "rows": rows}
     print(json.dumps(out), flush=True)
