@@ -24,8 +24,6 @@ def test_library_exports_every_declared_symbol():
 
 @pytest.mark.parametrize("k,nq", [(1, 2), (2, 3), (2, 4), (3, 5), (4, 6), (7, 9)])
 def test_tables_match_oracle(k, nq):
-    if k == 2 and nq == 4:
-        pytest.skip("pair not built")
     h = feod.HostSetup(1, 1, 1, k, nq)
     d = Discretisation(1, 1, 1, k, nq, 3.0, 1e-2)
     assert np.abs(h.nodes - d.nodes1d).max() < 1e-15
