@@ -788,6 +788,7 @@ feod_status feod_set_rho(feod_ctx* c, const double* rho_dev) {
 }
 
 constexpr double kInitRtol = 1e-3;  // relative CG tolerance of the Poisson initial guess
+constexpr int kScaleIters = 8;      // Newton steps of the 1D energy minimisation along the Poisson guess
 
 feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* opts_in,
                               feod_solver_report* rep_out) {
@@ -837,7 +838,31 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
                        o.partial_assembly);
     if (s != FEOD_OK) return finish(s);
     rep.cg_iters_total += cr.iters;
-    if (feod_status s2 = timed(c, "axpby", [&] { return launch_axpby(u, 1.0, ut, 0.0, nullptr, N, c->stream); });
+    // The p = 2 solution u2 has the right shape but, for p != 2, the wrong
+    // size.  Scale it to the minimiser of the energy along its ray:
+    // phi(alpha) = E(alpha u2) is convex, phi' = u2 . R(alpha u2) and
+    // phi'' = u2 . J(alpha u2) u2, so a few Newton steps on phi' = 0 do.
+    double alpha = 1.0;
+    if (c->p != 2.0) {
+      double* q = c->d_vec[V_DU];
+      for (int k = 0; k < kScaleIters; ++k) {
+        double g, h;
+        if (feod_status s2 = timed(c, "axpby", [&] { return launch_axpby(u, alpha, ut, 0.0, nullptr, N, c->stream); });
+            s2 != FEOD_OK)
+          return finish(s2);
+        if (feod_status s2 = apply_residual(c, u, R, 0); s2 != FEOD_OK) return finish(s2);
+        if (feod_status s2 = host_dot(c, ut, R, N, &g); s2 != FEOD_OK) return finish(s2);
+        if (feod_status s2 = apply_jvp(c, u, ut, q, nullptr, 0); s2 != FEOD_OK) return finish(s2);
+        if (feod_status s2 = host_dot(c, ut, q, N, &h); s2 != FEOD_OK) return finish(s2);
+        if (!(h > 0) || !std::isfinite(g)) break;  // flat or broken ray: keep what we have
+        double next = alpha - g / h;
+        if (!(next > 0)) next = 0.5 * alpha;  // stay on the positive ray
+        const bool done = std::fabs(next - alpha) <= 1e-3 * alpha;
+        alpha = next;
+        if (done) break;
+      }
+    }
+    if (feod_status s2 = timed(c, "axpby", [&] { return launch_axpby(u, alpha, ut, 0.0, nullptr, N, c->stream); });
         s2 != FEOD_OK)
       return finish(s2);
   } else {
