@@ -83,7 +83,7 @@ typedef struct {
  * tolerance: eta_j = min(0.1, sqrt(||R_j||/||R_0||)), raised to at least
  * 0.5 rtol ||M b|| / ||R_j|| (no tighter than the stopping test needs) and
  * floored by cg_rtol_floor.  The p = 2 initial guess (init_poisson) is a CG
- * solve to 1e-3 relative, scaled (for p != 2) to the minimiser of the energy
+ * solve to 1e-1 relative, scaled (for p != 2) to the minimiser of the energy
  * along its ray by Newton steps on alpha -> u2 . R(alpha u2).
  * The line search is Armijo backtracking on the energy (c = 1e-4, halving,
  * at most max_ls halvings).  check_every: CG reads its residual norm back to
