@@ -872,6 +872,8 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
         s != FEOD_OK)
       return finish(s);
   }
+  bool have_energy = false;  // energy_u holds E(u) for the current u
+  double energy_u = 0.0;
   for (int it = 0;; ++it) {
     if (feod_status s = apply_residual(c, u, R, 0); s != FEOD_OK) return finish(s);
     double nr2;
@@ -906,12 +908,18 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
         s != FEOD_OK)
       return finish(s);
     rep.cg_iters_total += cr.iters;
-    // Armijo backtracking on the energy
+    // Armijo backtracking on the energy.  E(u) is known when the last step
+    // came out of the line search: u was formed by the same axpby as the
+    // accepted trial point, so the energy is bitwise the trial's.
     double E0, slope;
-    if (feod_status s = host_energy(c, u, &E0); s != FEOD_OK) return finish(s);
+    if (have_energy)
+      E0 = energy_u;
+    else if (feod_status s = host_energy(c, u, &E0); s != FEOD_OK)
+      return finish(s);
     if (feod_status s = host_dot(c, R, du, N, &slope); s != FEOD_OK) return finish(s);
     if (!std::isfinite(E0) || !std::isfinite(slope)) return finish(fail(c, FEOD_ENONFINITE, "non-finite energy"));
     double t = 1.0;
+    have_energy = false;
     if (std::fabs(slope) > 1e-13 * std::fabs(E0)) {
       if (slope >= 0) return finish(fail(c, FEOD_EBREAKDOWN, "Newton direction is not a descent direction"));
       int h = 0;
@@ -921,7 +929,11 @@ feod_status feod_newton_solve(feod_ctx* c, double* u, const feod_solver_opts* op
           return finish(s);
         double Et;
         if (feod_status s = host_energy(c, ut, &Et); s != FEOD_OK) return finish(s);
-        if (std::isfinite(Et) && Et <= E0 + 1e-4 * t * slope) break;
+        if (std::isfinite(Et) && Et <= E0 + 1e-4 * t * slope) {
+          energy_u = Et;  // the energy of the next u
+          have_energy = true;
+          break;
+        }
         if (h >= o.max_ls) return finish(fail(c, FEOD_EBREAKDOWN, "line search failed"));
         t *= 0.5;
       }
