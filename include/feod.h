@@ -191,7 +191,8 @@ feod_status feod_element_vectors(feod_ctx* ctx, int32_t op, const double* u, con
  * with J_D from forward-mode dual numbers at each quadrature point and B^T J_D B
  * contracted by sum factorisation.  Ke: device, count * (k+1)^6 doubles, one
  * row-major (k+1)^3 x (k+1)^3 matrix per element in local node order
- * a + (k+1)(b + (k+1) c).  FP64; FEOD_EUNSUPPORTED for k > 4. */
+ * a + (k+1)(b + (k+1) c).  FP64; FEOD_EUNSUPPORTED for k > 4.  count = 0
+ * writes nothing (Ke may then be NULL). */
 feod_status feod_element_tangents(feod_ctx* ctx, const double* u, int64_t first, int64_t count,
                                   double* Ke);
 

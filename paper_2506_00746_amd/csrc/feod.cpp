@@ -694,9 +694,10 @@ feod_status feod_element_vectors(feod_ctx* c, int32_t op, const double* u, const
 feod_status feod_element_tangents(feod_ctx* c, const double* u, int64_t first, int64_t count, double* Ke) {
   TRY(need_bound(c));
   TRY(check_vec(c, u, "u"));
-  TRY(check_vec(c, Ke, "Ke"));
   if (first < 0 || count < 0 || first + count > c->lat.E)
     return fail(c, FEOD_EINVAL, "element range outside the mesh");
+  if (count == 0) return FEOD_OK;  // nothing to write (Ke may be NULL)
+  TRY(check_vec(c, Ke, "Ke"));
   if (count > INT32_MAX) return fail(c, FEOD_EINVAL, "too many elements in one call");
   ElemLaunch fn = c->L->tangent[c->curved ? 1 : 0][pow_kind(c->p)];
   if (!fn) return fail(c, FEOD_EUNSUPPORTED, "element tangents are built for k <= 4 only");
@@ -711,9 +712,10 @@ feod_status feod_element_tangents(feod_ctx* c, const double* u, int64_t first, i
 feod_status feod_element_tangents_elm(feod_ctx* c, const double* u, int64_t first, int64_t count, double* Ke) {
   TRY(need_bound(c));
   TRY(check_vec(c, u, "u"));
-  TRY(check_vec(c, Ke, "Ke"));
   if (first < 0 || count < 0 || first + count > c->lat.E)
     return fail(c, FEOD_EINVAL, "element range outside the mesh");
+  if (count == 0) return FEOD_OK;  // nothing to write (Ke may be NULL)
+  TRY(check_vec(c, Ke, "Ke"));
   if (count > INT32_MAX) return fail(c, FEOD_EINVAL, "too many elements in one call");
   ElemLaunch fn = c->L->prec[0].op[OP_ELM][c->curved ? 1 : 0][pow_kind(c->p)];
   if (!fn) return fail(c, FEOD_EUNSUPPORTED, "element-level tangents are built for k <= 4 only");

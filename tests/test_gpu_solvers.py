@@ -151,3 +151,6 @@ def test_binding_argument_handling():
         prob.element_tangents(u, 0, 1, out=torch.empty((1, ne, ne), dtype=torch.float64))
     with pytest.raises(ValueError):
         prob.element_tangents(u, 0, 2, out=torch.empty((1, ne, ne), dtype=torch.float64, device="cuda:0"))
+    # an empty element range is a no-op for both tangent variants
+    for method in ("res", "elm"):
+        assert prob.element_tangents(u, first=3, count=0, method=method).shape == (0, ne, ne)
