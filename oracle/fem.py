@@ -62,12 +62,21 @@ def flux(g: np.ndarray, p: float, eps: float) -> np.ndarray:
 
 
 def tangent_matrix(g: np.ndarray, p: float, eps: float) -> np.ndarray:
-    """dF/dg = a^(r-1) (a I + (p-2) g g^T), hand-derived from F(g)."""
+    """dF/dg = a^(r-1) (a I + (p-2) g g^T), hand-derived from F(g).
+
+    a = 0 only when eps = 0 and g = 0 (allowed for p >= 2).  There the
+    formula reads 0^(r-1) * 0; its limit as g -> 0 is taken instead: the
+    matrix has eigenvalues a^r and (p-1) a^r (with eps = 0, |g|^2 = a), so it
+    tends to 0 for p > 2 and equals I for p = 2."""
     r = (p - 2.0) / 2.0
     a = eps * eps + np.sum(g * g, axis=-1)
     eye = np.eye(3)
     T = a[..., None, None] * eye + (p - 2.0) * g[..., :, None] * g[..., None, :]
-    return (a ** (r - 1.0))[..., None, None] * T
+    zero = a == 0.0
+    out = (np.where(zero, 1.0, a) ** (r - 1.0))[..., None, None] * T
+    if np.any(zero):
+        out[zero] = eye if p == 2.0 else 0.0
+    return out
 
 
 def flux_tangent(g: np.ndarray, dg: np.ndarray, p: float, eps: float) -> np.ndarray:
@@ -333,10 +342,11 @@ class Discretisation:
         Md = sps.diags(self.mask)
         return (Md @ K @ Md).tocsr()
 
-    def grad_rho(self, u, lam):
-        """dPhi/drho_e = -sum_q w detJ a^r grad(Mu) . grad(M lam), per element."""
+    def grad_rho(self, u, lam, elems=None):
+        """dPhi/drho_e = -sum_q w detJ a^r grad(Mu) . grad(M lam), per element
+        (all elements, or only the listed ones: entries of the others are 0)."""
         out = np.zeros(self.E)
-        for ch in self._chunks(np.arange(self.E)):
+        for ch in self._chunks(self._all(elems)):
             _, detJ, Jinv, _ = self.geometry(ch)
             g = physical_gradient(Jinv, self.ref_gradient(self.gather(u, ch)))
             gl = physical_gradient(Jinv, self.ref_gradient(self.gather(lam, ch)))

@@ -37,6 +37,20 @@ def _fd_energy_error():
     return relerr(fd, R)
 
 
+def _fd_jvp_eps0_error():
+    """Central differences of R at eps = 0, p = 3.5, with u zero on half of
+    the mesh (zero gradient there: the a = 0 limit of the tangent is used;
+    the formula itself gives 0^(-1/4) * 0)."""
+    w = Workload("t", 4, 2, 2, 2, 3, 3.5, 0.0, 13, rho=True)
+    inp = make_inputs(w)
+    d = Discretisation(4, 2, 2, 2, 3, 3.5, 0.0, rho=inp["rho"])
+    I = np.arange(d.N) % d.Lx
+    u, v = np.where(I < d.Lx // 2, 0.0, 0.5 * inp["u"]), inp["v"]
+    h = 1e-6 * np.linalg.norm(u) / np.linalg.norm(v)
+    fd = (d.residual(u + h * v) - d.residual(u - h * v)) / (2 * h)
+    return relerr(d.jvp(u, v), fd)
+
+
 def _patch_error():
     w = Workload("t", 3, 2, 3, 2, 3, 3.0, 1e-2, 7, perturb=True)
     d = Discretisation(3, 2, 3, 2, 3, 3.0, 1e-2, vertices=make_inputs(w)["vertices"])
@@ -53,7 +67,7 @@ def _kron_error():
     return relerr(d.residual(u), d.mask * (K @ (d.mask * u) - b))
 
 
-PINS = {"fd_jvp": (_fd_jvp_error, 1e-7), "fd_energy": (_fd_energy_error, 1e-7),
+PINS = {"fd_jvp": (_fd_jvp_error, 1e-7), "fd_jvp_eps0": (_fd_jvp_eps0_error, 1e-7), "fd_energy": (_fd_energy_error, 1e-7),
         "patch": (_patch_error, 1e-13), "kron": (_kron_error, 1e-12)}
 
 
@@ -67,6 +81,23 @@ def _bad_tangent_sign(g, p, eps):
     a = eps * eps + np.sum(g * g, axis=-1)
     T = a[..., None, None] * np.eye(3) - (p - 2.0) * g[..., :, None] * g[..., None, :]
     return (a ** (r - 1.0))[..., None, None] * T
+
+
+def _bad_tangent_limit(g, p, eps):           # identity at a = 0 whatever p (the p = 2 limit)
+    r = (p - 2.0) / 2.0
+    a = eps * eps + np.sum(g * g, axis=-1)
+    T = a[..., None, None] * np.eye(3) + (p - 2.0) * g[..., :, None] * g[..., None, :]
+    out = (np.where(a == 0, 1.0, a) ** (r - 1.0))[..., None, None] * T
+    out[a == 0] = np.eye(3)
+    return out
+
+
+def _bad_tangent_no_limit(g, p, eps):         # the formula as written: 0^(r-1) * 0 = nan at a = 0
+    r = (p - 2.0) / 2.0
+    a = eps * eps + np.sum(g * g, axis=-1)
+    T = a[..., None, None] * np.eye(3) + (p - 2.0) * g[..., :, None] * g[..., None, :]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        return (a ** (r - 1.0))[..., None, None] * T
 
 
 def _bad_physical_gradient(Jinv, ghat):       # Jg^{-1} instead of Jg^{-T}
@@ -90,6 +121,8 @@ def _bad_energy_density(g, p, eps):
 MUTANTS = [
     ("tangent_matrix", _bad_tangent_no_p2, "fd_jvp"),
     ("tangent_matrix", _bad_tangent_sign, "fd_jvp"),
+    ("tangent_matrix", _bad_tangent_limit, "fd_jvp_eps0"),
+    ("tangent_matrix", _bad_tangent_no_limit, "fd_jvp_eps0"),
     ("physical_gradient", _bad_physical_gradient, "patch"),
     ("pull_back", _bad_pull_back, "patch"),
     ("flux", _bad_flux_exponent, "fd_energy"),
@@ -102,7 +135,8 @@ def test_planted_mistake_fails_its_pin(monkeypatch, name, bad, pin):
     fn, tol = PINS[pin]
     assert fn() < tol                    # the true oracle passes
     monkeypatch.setattr(fem, name, bad)
-    assert fn() > 10 * tol               # the planted mistake fails
+    err = fn()
+    assert not err <= 10 * tol           # the planted mistake fails (or gives nan)
 
 
 def test_swapped_gradient_axes_fail_kronecker(monkeypatch):

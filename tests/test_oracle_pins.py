@@ -154,3 +154,59 @@ def test_element_tangents_assemble_to_jacobian_and_match_fd():
         du[d.elem_dofs[e, j]] = h
         fd = (d.element_residual(u + du, [e]) - d.element_residual(u - du, [e]))[0] / (2 * h)
         assert relerr(Ke[e][:, j], fd) < 1e-7
+
+
+# ---- eps = 0 where the gradient vanishes (a = eps^2 + |g|^2 = 0) ----------------
+
+def _vanishing_on_half(d, u):
+    """u with every node of the lower half (x index below Lx/2) set to 0, so
+    the elements there have a zero gradient at every quadrature point."""
+    I = np.arange(d.N) % d.Lx
+    return np.where(I < d.Lx // 2, 0.0, u)
+
+
+@pytest.mark.parametrize("p", [2.0, 2.5, 3.0, 4.0])
+def test_eps0_at_zero_is_the_limit_of_the_closed_form(p):
+    """At eps = 0, R(0) = -M b and E(0) = 0; J(0) is the eps -> 0 limit of
+    J(0) = eps^(p-2) K: the Kronecker Laplacian for p = 2, zero for p > 2."""
+    d, inp = _disc(2, 3, 2, 2, 3, p, 0.0)
+    K, b = kronecker_laplacian(gll_nodes(2), 2, 3, 2)
+    M = d.mask
+    z = np.zeros(d.N)
+    assert relerr(d.residual(z), -M * b) < 1e-15
+    assert d.energy(z) == 0.0
+    jv = d.jvp(z, inp["v"])
+    if p == 2.0:
+        assert relerr(jv, M * (K @ (M * inp["v"]))) < 1e-12
+    else:
+        assert np.all(jv == 0.0)
+    Ke = d.element_tangents(z, np.arange(d.E))
+    assert np.all(np.isfinite(Ke))
+
+
+@pytest.mark.parametrize("p", [4.0, 3.5, 3.0, 2.5])
+@pytest.mark.parametrize("perturb", [False, True])
+def test_eps0_jvp_matches_central_difference_where_gradient_vanishes(p, perturb):
+    """J(u) v against central differences of R at eps = 0 with u zero on half
+    the mesh.  At a zero-gradient point the difference quotient is
+    |h grad v|^(p-2) grad v = O(h^(p-2)) against the limit 0 of the tangent.
+    For p >= 3.5 that is below 1e-7 at h = 1e-6; for p = 3 and 2.5 it
+    dominates, and the error must shrink at exactly that rate (a wrong finite
+    limit at a = 0 would leave an error that does not shrink)."""
+    d, inp = _disc(4, 2, 2, 2, 3, p, 0.0, perturb=perturb, rho=True)
+    u, v = _vanishing_on_half(d, 0.5 * inp["u"]), inp["v"]
+    jv = d.jvp(u, v)
+    assert np.all(np.isfinite(jv))
+    err = {}
+    for hs in (1e-4, 1e-6):
+        h = hs * np.linalg.norm(u) / np.linalg.norm(v)
+        fd = (d.residual(u + h * v) - d.residual(u - h * v)) / (2 * h)
+        err[hs] = relerr(jv, fd)
+    if p >= 3.5:
+        assert err[1e-6] < 1e-7
+    else:
+        rate = np.log10(err[1e-4] / err[1e-6]) / 2.0
+        assert abs(rate - (p - 2.0)) < 0.05
+        assert err[1e-6] < 1e-6 ** (p - 2.0)
+    # the Euler identity J(u) u = (p-1) A(u) of the homogeneous flux holds there too
+    assert relerr(d.jvp(u, u), (p - 1) * d.mask * d.apply_unmasked(u)) < 1e-13
