@@ -27,15 +27,22 @@ __device__ __forceinline__ float fe_rsqrt(float x) { return __builtin_amdgcn_rsq
 // a^r and, for dual numbers, d(a^r) = r a^(r-1) da, without divisions:
 //   r = 1/2:  a^r = a t, t = a^(-1/2);  d = t da / 2
 //   r = 1/4:  a^r = s u, s = a t, u = s^(-1/2);  d = a^r t^2 da / 4
+// a = 0 happens only with eps = 0 where the gradient vanishes (p >= 2 there).
+// Then a^r = 0 for r > 0, and the tangent of F = a^r g tends to 0 (its size
+// is at most max(1, p-1) a^r), so both parts are 0; the chains above would
+// give 0 * inf = NaN.
 template <int PK, class T>
 __device__ __forceinline__ T apow(T a, T r) {
   if constexpr (PK == POW_ZERO) return T(1);
   else if constexpr (PK == POW_QUARTER) {
     const T s = a * fe_rsqrt(a);
-    return s * fe_rsqrt(s);
-  } else if constexpr (PK == POW_HALF) return a * fe_rsqrt(a);
-  else if constexpr (PK == POW_ONE) return a;
-  else return fe_pow(a, r);
+    const T c = s * fe_rsqrt(s);
+    return a > T(0) ? c : T(0);
+  } else if constexpr (PK == POW_HALF) {
+    const T c = a * fe_rsqrt(a);
+    return a > T(0) ? c : T(0);
+  } else if constexpr (PK == POW_ONE) return a;
+  else return fe_pow(a, r);  // pow(0, r) = 0 for r > 0; r < 0 needs eps > 0
 }
 
 template <int PK, class T>
@@ -46,15 +53,17 @@ __device__ __forceinline__ dual<T> apow(dual<T> a, T r) {
     const T t = fe_rsqrt(a.v);
     const T s = a.v * t;
     const T c = s * fe_rsqrt(s);
-    return {c, T(0.25) * c * t * t * a.d};
+    const T d = T(0.25) * c * t * t * a.d;
+    return {a.v > T(0) ? c : T(0), a.v > T(0) ? d : T(0)};
   } else if constexpr (PK == POW_HALF) {
     const T t = fe_rsqrt(a.v);
-    return {a.v * t, T(0.5) * t * a.d};
+    const T c = a.v * t, d = T(0.5) * t * a.d;
+    return {a.v > T(0) ? c : T(0), a.v > T(0) ? d : T(0)};
   } else if constexpr (PK == POW_ONE) {
     return a;
   } else {
     const T pv = fe_pow(a.v, r);
-    return {pv, r * pv / a.v * a.d};
+    return {pv, a.v > T(0) ? r * pv / a.v * a.d : T(0)};
   }
 }
 
@@ -78,7 +87,7 @@ template <int PK, class T>
 __device__ __forceinline__ void flux_tangent_hand(const T g[3], const T dg[3], T eps2, T r, T dF[3]) {
   const T a = g[0] * g[0] + g[1] * g[1] + g[2] * g[2] + eps2;
   const T gd = g[0] * dg[0] + g[1] * dg[1] + g[2] * dg[2];
-  T c, k;  // a^r and 2 r a^(r-1)
+  T c, k;  // a^r and 2 r a^(r-1); both 0 at a = 0 (eps = 0, zero gradient), see apow
   if constexpr (PK == POW_ZERO) {
     c = T(1);
     k = T(0);
@@ -86,16 +95,18 @@ __device__ __forceinline__ void flux_tangent_hand(const T g[3], const T dg[3], T
     const T t = fe_rsqrt(a), s = a * t;
     c = s * fe_rsqrt(s);
     k = T(0.5) * c * t * t;
+    c = a > T(0) ? c : T(0);
+    k = a > T(0) ? k : T(0);
   } else if constexpr (PK == POW_HALF) {
     const T t = fe_rsqrt(a);
-    c = a * t;
-    k = t;
+    c = a > T(0) ? a * t : T(0);
+    k = a > T(0) ? t : T(0);
   } else if constexpr (PK == POW_ONE) {
     c = a;
     k = T(2);
   } else {
     c = fe_pow(a, r);
-    k = T(2) * r * c / a;
+    k = a > T(0) ? T(2) * r * c / a : T(0);
   }
   const T kg = k * gd;
 #pragma unroll

@@ -70,9 +70,11 @@ def test_mixed_precision_error_vs_fp64_oracle(w):
     e_j = relerr(jv, ora.jvp(inp["u"], inp["v"]))
     lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, ora.N)
     e_g = relerr(host(prob.grad_rho(u, dev(lam), prec="mixed")), ora.grad_rho(inp["u"], lam))
+    e_e = abs(host(prob.energy(u, prec="mixed"))[0] - ora.energy(inp["u"])) / abs(ora.energy(inp["u"]))
     print(f"mixed-precision rel. L2 error vs FP64 oracle [{w.name}]: residual {e_r:.2e} "
-          f"jvp {e_j:.2e} grad {e_g:.2e}")
-    assert e_r < 1e-4 and e_j < 1e-4 and e_g < 1e-4
+          f"jvp {e_j:.2e} grad {e_g:.2e} energy {e_e:.2e}")
+    # FP32 B, D, B^T with FP32 accumulation: about 1e-7 measured at these sizes
+    assert e_r <= 5e-6 and e_j <= 5e-6 and e_g <= 5e-6 and e_e <= 5e-6
 
 
 @pytest.mark.parametrize("w", SMALL, ids=IDS)
@@ -191,7 +193,8 @@ def test_jacobian_diagonal_matches_assembled_oracle(w):
     d_o = ora.jacobian(inp["u"]).diagonal()
     assert relerr(d, d_o) <= 1e-12
     dm = host(prob.jacobian_diagonal(dev(inp["u"]), prec="mixed"))
-    assert relerr(dm, d_o) <= 1e-5
+    print(f"[{w.name}] mixed diagonal rel. error vs FP64 oracle: {relerr(dm, d_o):.2e}")
+    assert relerr(dm, d_o) <= 5e-6
 
 
 @pytest.mark.parametrize("w", [SMALL[0], SMALL[1], SMALL[2], SMALL[3], SMALL[4], SMALL[5], SMALL[7], SMALL[8]],
@@ -268,7 +271,9 @@ def test_partial_assembly_jvp_equals_fused(w):
         a = host(prob.jacobian_apply_pa(v, prec=prec))
         b = host(prob.jacobian_apply(u, v, prec=prec))
         assert np.array_equal(a, b), prec
-    assert relerr(host(prob.jacobian_apply_pa(v, prec="mixed")), ora.jvp(inp["u"], inp["v"])) < 1e-5
+    e_pa = relerr(host(prob.jacobian_apply_pa(v, prec="mixed")), ora.jvp(inp["u"], inp["v"]))
+    print(f"[{w.name}] mixed partial-assembly JVP rel. error vs FP64 oracle: {e_pa:.2e}")
+    assert e_pa <= 5e-6
     prob.pa_setup(u)
     assert relerr(host(prob.jacobian_apply_pa(v)), ora.jvp(inp["u"], inp["v"])) <= 1e-12
 
@@ -297,7 +302,9 @@ def test_degenerate_meshes_match_oracle(w):
     assert abs(host(prob.energy(u))[0] - e_o) <= 1e-12 * abs(e_o)
     lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, ora.N)
     assert relerr(host(prob.grad_rho(u, dev(lam))), ora.grad_rho(inp["u"], lam)) <= 1e-12
-    assert relerr(host(prob.jacobian_apply(u, v, prec="mixed")), jv_o) <= 1e-4
+    e_m = relerr(host(prob.jacobian_apply(u, v, prec="mixed")), jv_o)
+    print(f"[{w.name}] mixed JVP rel. error vs FP64 oracle: {e_m:.2e}")
+    assert e_m <= 5e-6
     prob.pa_setup(u)
     assert torch.equal(prob.jacobian_apply_pa(v), jv)
 
@@ -321,3 +328,73 @@ def test_all_dirichlet_mesh_gives_exact_zeros():
     grad, lam, rep = prob.adjoint_gradient(us, dev(ora.b))
     assert rep["status"] == 0 and rep["cg_iters_total"] == 0
     assert not host(lam).any() and not host(grad).any()
+
+
+EPS0 = [
+    Workload("eps0-p3-affine", 4, 3, 2, 2, 3, 3.0, 0.0, 44),
+    Workload("eps0-p3-curved", 3, 2, 3, 2, 3, 3.0, 0.0, 45, perturb=True, rho=True),
+    Workload("eps0-p2.5-affine", 3, 3, 2, 3, 5, 2.5, 0.0, 46, rho=True),
+    Workload("eps0-p2.5-curved", 2, 3, 2, 3, 5, 2.5, 0.0, 47, perturb=True, rho=True),
+    Workload("eps0-p2.5-q7-curved", 2, 2, 2, 7, 9, 2.5, 0.0, 48, perturb=True),
+]
+
+
+def _vanishing_on_half(w, u):
+    """u with every node of the lower x half set to 0: the elements there have
+    a zero gradient (a = eps^2 + |g|^2 = 0 at eps = 0) at every point."""
+    Lx = w.k * w.nx + 1
+    return np.where(np.arange(u.size) % Lx < Lx // 2, 0.0, u)
+
+
+@pytest.mark.parametrize("w", EPS0, ids=[w.name for w in EPS0])
+def test_eps0_zero_gradient(w):
+    """eps = 0 where the gradient vanishes (the limit of Eq. (2)'s J_D there
+    is 0 for p > 2): R(0) = -M b, E(0) = 0 and J(0) v = 0 exactly, in both
+    precisions; and with u zero on half the mesh every operator matches the
+    oracle element by element."""
+    announce("eps = 0 zero gradient", w)
+    prob, ora, inp = setup(w)
+    N = ora.N
+    bm = ora.mask * feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load
+    z = dev(np.zeros(N))
+    v = dev(inp["v"])
+    for prec in ("fp64", "mixed"):
+        r0 = host(prob.residual(z, prec=prec))
+        assert np.array_equal(r0, -bm), prec
+        assert relerr(r0, -ora.mask * ora.b) <= 1e-12
+        assert not host(prob.jacobian_apply(z, v, prec=prec)).any(), prec
+        r2, jv2 = prob.residual_and_jvp(z, v, prec=prec)
+        assert np.array_equal(host(r2), -bm) and not host(jv2).any(), prec
+        assert not host(prob.jacobian_diagonal(z, prec=prec)).any(), prec
+        assert not host(prob.grad_rho(z, v, prec=prec)).any(), prec
+        assert host(prob.energy(z, prec=prec))[0] == 0.0, prec
+    if w.k <= 4:
+        assert not host(prob.element_tangents(z)).any()
+        assert not host(prob.element_tangents(z, method="elm")).any()
+    assert not ora.jvp(np.zeros(N), inp["v"]).any()
+    # half the mesh at zero gradient, the other half random: every operator
+    uh = _vanishing_on_half(w, inp["u"])
+    u = dev(uh)
+    r_o, jv_o = ora.residual(uh), ora.jvp(uh, inp["v"])
+    assert relerr(host(prob.residual(u)), r_o) <= 1e-12
+    jv = prob.jacobian_apply(u, v)
+    assert relerr(host(jv), jv_o) <= 1e-12
+    r2, jv2 = prob.residual_and_jvp(u, v)
+    assert relerr(host(r2), r_o) <= 1e-12 and relerr(host(jv2), jv_o) <= 1e-12
+    e_o = ora.energy(uh)
+    assert abs(host(prob.energy(u))[0] - e_o) <= 1e-12 * abs(e_o)
+    lam = np.random.default_rng(w.seed + 100).uniform(-1, 1, N)
+    assert relerr(host(prob.grad_rho(u, dev(lam))), ora.grad_rho(uh, lam)) <= 1e-12
+    assert relerr(host(prob.jacobian_diagonal(u)), ora.jacobian(uh).diagonal()) <= 1e-12
+    if w.k <= 4:
+        Ko = ora.element_tangents(uh, np.arange(ora.E))
+        assert relerr(host(prob.element_tangents(u)), Ko) <= 1e-12
+        assert relerr(host(prob.element_tangents(u, method="elm")), Ko) <= 1e-12
+    prob.set_tangent_mode("hand")
+    assert relerr(host(prob.jacobian_apply(u, v)), jv_o) <= 1e-12
+    prob.set_tangent_mode("dual")
+    prob.pa_setup(u)
+    assert torch.equal(prob.jacobian_apply_pa(v), jv)
+    e_m = relerr(host(prob.jacobian_apply(u, v, prec="mixed")), jv_o)
+    print(f"[{w.name}] mixed JVP rel. error vs FP64 oracle at eps = 0: {e_m:.2e}")
+    assert e_m <= 5e-6
