@@ -124,8 +124,11 @@ typedef struct {
 
 /* Fill opts with defaults: rtol 1e-10, cg_rtol_floor 1e-12, max_newton 50,
  * max_cg 20000, max_ls 30, check_every 10, FP64, init_poisson 1, jacobi 1,
- * partial_assembly 1 (measured fastest on the 48^3 Q2 and 32^3 Q3 workloads:
- * Jacobi halves the CG iterations, partial assembly saves 7-10%). */
+ * partial_assembly 0.  Jacobi preconditioning halves the CG iterations and
+ * the Newton time on the 48^3 Q2 and 32^3 Q3 workloads.  Partial assembly
+ * measured within 1.5% of the fused Jacobian action over whole Newton solves
+ * on both (31.03 vs 30.99 ms and 39.00 vs 38.58 ms), so the default keeps the
+ * fused action, whose quadrature data never leaves the registers. */
 void feod_default_opts(feod_solver_opts* opts);
 
 /* Build the mesh, element-to-DOF map G, transposed map for G^T, 1D tables and
@@ -217,9 +220,14 @@ feod_status feod_pa_setup(feod_ctx* ctx, const double* u, feod_prec prec);
  * (FEOD_ESTATE otherwise).  v, jv: device, length N. */
 feod_status feod_jacobian_apply_pa(feod_ctx* ctx, const double* v, double* jv, feod_prec prec);
 
-/* Energy E(u) = sum_e rho_e int_e (1/p)(eps^2+|grad Mu|^2)^(p/2) - b^T M u,
- * whose gradient is R (line-search merit function).  e_dev: device, 1 double. */
-feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev);
+/* Energy E(u) = sum_e rho_e int_e (1/p)(eps^2+|grad Mu|^2)^(p/2) - b^T M u of
+ * the p-Laplacian model problem, the functional whose gradient is the
+ * residual of Eq. (1) (R = dE/du, quadrature included); the Newton line
+ * search uses it as its merit function.  e_dev: device, 1 double.  prec:
+ * FEOD_MIXED evaluates the element energies in FP32 (their sum and b^T M u in
+ * FP64); the Newton driver always uses FP64, since its line search compares
+ * energies that differ in their last digits. */
+feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev, feod_prec prec);
 
 /* diag(J(u)): the diagonal of the masked Jacobian of Eq. (2) (boundary rows
  * 0), by sum-factorised quadrature of grad phi_i^T J_D grad phi_i followed by
@@ -227,9 +235,15 @@ feod_status feod_energy(feod_ctx* ctx, const double* u, double* e_dev);
 feod_status feod_jacobian_diagonal(feod_ctx* ctx, const double* u, double* diag,
                                    feod_prec prec);
 
-/* Damped Newton-CG on R(u) = 0.  u: device, length N; in: initial guess (used
+/* Damped inexact Newton-CG on R(u) = 0 of Eq. (1), each step solving
+ * J(u) du = -R(u) by CG with the matrix-free Jacobian action of Eq. (2) (J is
+ * symmetric, positive definite on the interior DOFs), the step damped by the
+ * line search on feod_energy.  u: device, length N; in: initial guess (used
  * unless opts->init_poisson), out: solution with boundary entries 0.  opts may
- * be NULL (defaults).  report may be NULL.  Synchronises the stream. */
+ * be NULL (defaults).  report may be NULL.  Synchronises the stream.  With
+ * FEOD_MIXED the Jacobian actions inside CG run in FP32; residuals, energies,
+ * CG vectors and inner products stay FP64, so the stopping test is the same
+ * FP64 one. */
 feod_status feod_newton_solve(feod_ctx* ctx, double* u, const feod_solver_opts* opts,
                               feod_solver_report* report);
 

@@ -18,8 +18,8 @@
 //   D  y-back         line (c,qx) -> LDS.
 //   E  x-back         line (c,b): D1 element residual entries written
 //                     contiguously to the output E-vector, laid out
-//                     [ez][ey][c][b][ex][a] (G^T is the separate deterministic
-//                     gather).
+//                     [e][c][b][a] (each element's entries contiguous; G^T is
+//                     the separate deterministic gather).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -255,11 +255,7 @@ __device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const
   constexpr int XS = D1 * NQ * XQ;
   constexpr int NG = UNIT ? NF - 1 : NF;  // gathered fields
   for (int l = tid; l < EB * D1 * D1; l += NT) {
-#if FEOD_EVEC_ROWMAJOR
-    const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: consecutive elements of the row
-#else
     const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
-#endif
     const int c = cb / D1, b = cb - c * D1;
     T in[NF][D1];
     if (el < n_valid && P.emap != nullptr) {
@@ -882,20 +878,11 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
 
   // ---- E: x-back: out[a] = sum_qx D K0 + B K1 -> E-vector --------------------
   for (int l = tid; l < EB * D1 * D1; l += NT) {
-#if FEOD_EVEC_ROWMAJOR
-    const int cb = l / EB, el = l - cb * EB;  // consecutive lanes: adjacent E-vector stretches
-    const int c = cb / D1, b = cb - c * D1;
-    if (el >= n_valid) continue;
-    const int64_t pos = ELM ? ((int64_t)(e0 + el) * Ne + cb * D1) * Ne + blockIdx.y  // column of K_e
-                            : ((((int64_t)sE[el][2] * P.ny + sE[el][1]) * D1 + c) * D1 + b) * P.nx * D1 +
-                                  (int64_t)sE[el][0] * D1;
-#else
     const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
     const int c = cb / D1, b = cb - c * D1;
     if (el >= n_valid) continue;
     const int64_t pos = ELM ? ((int64_t)(e0 + el) * Ne + cb * D1) * Ne + blockIdx.y  // column of K_e
                             : (int64_t)(e0 + el) * Ne + cb * D1;
-#endif
     constexpr int OSTR = ELM ? Ne : 1;  // output stride along a (a K_e column for ELM)
     if constexpr (DIAG) {
       const T* k = Xs + el * L::XSTR + c * L::XC + b;

@@ -328,8 +328,10 @@ feod_status host_dot(feod_ctx* c, const double* x, const double* y, int64_t n, d
   return read_scalars(c, S_T, 1, val);
 }
 
-feod_status energy_dev(feod_ctx* c, const double* u, double* e_dev) {
-  TRY(run_element(c, OP_ENERGY, 0, params(c, u, nullptr, c->d_elem, nullptr, 0)));
+// E(u) = sum of the per-element energies (element kernel in precision prec,
+// FP64 accumulation) - b . M u (FP64)
+feod_status energy_dev(feod_ctx* c, const double* u, double* e_dev, int prec = 0) {
+  TRY(run_element(c, OP_ENERGY, prec, params(c, u, nullptr, c->d_elem, nullptr, prec)));
   TRY(dot(c, c->d_elem, nullptr, c->lat.E, c->d_sc + S_A));
   return dot(c, c->d_bm, u, c->lat.N, e_dev, -1.0, c->d_sc + S_A);
 }
@@ -487,7 +489,7 @@ void feod_default_opts(feod_solver_opts* o) {
   o->prec = FEOD_FP64;
   o->init_poisson = 1;
   o->jacobi = 1;
-  o->partial_assembly = 1;
+  o->partial_assembly = 0;
 }
 
 feod_status feod_setup_mesh(const feod_mesh_desc* d, feod_ctx** out) {
@@ -750,12 +752,13 @@ feod_status feod_jacobian_apply_pa(feod_ctx* c, const double* v, double* jv, feo
   return timed(c, "gather_transpose", [&] { return gather_t(c, c->d_Y0, nullptr, pr == 1, nullptr, jv, nullptr); });
 }
 
-feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev) {
+feod_status feod_energy(feod_ctx* c, const double* u, double* e_dev, feod_prec prec) {
   TRY(need_bound(c));
+  TRY(check_prec(c, prec));
   TRY(check_vec(c, u, "u"));
   TRY(check_vec(c, e_dev, "e_dev"));
   if (overlap(u, (size_t)c->lat.N * 8, e_dev, 8)) return fail(c, FEOD_EINVAL, "e_dev overlaps u");
-  return energy_dev(c, u, e_dev);
+  return energy_dev(c, u, e_dev, prec == FEOD_MIXED);
 }
 
 feod_status feod_jacobian_diagonal(feod_ctx* c, const double* u, double* diag, feod_prec prec) {

@@ -171,17 +171,9 @@ bool make_lattice(int nx, int ny, int nz, int k, Lattice* L, std::string* msg) {
   std::vector<int32_t> fill(L->toff.begin(), L->toff.end() - 1);
   for (int64_t j = 0; j < L->E * L->Ne; ++j) {  // ascending element => ascending within rows
     const int32_t g = L->emap[j];
-    if (g >= 0) L->tidx[fill[g]++] = (int32_t)evec_position(*L, j / L->Ne, (int)(j % L->Ne));
+    if (g >= 0) L->tidx[fill[g]++] = (int32_t)j;  // E-vector position e * Ne + local node
   }
   return true;
-}
-
-int64_t evec_position(const Lattice& L, int64_t e, int local) {
-  const int D1 = L.k + 1;
-  const int a = local % D1, b = (local / D1) % D1, c = local / (D1 * D1);
-  const int64_t ex = e % L.nx, ey = (e / L.nx) % L.ny, ez = e / ((int64_t)L.nx * L.ny);
-  if (!FEOD_EVEC_ROWMAJOR) return e * L.Ne + local;
-  return ((((ez * L.ny + ey) * D1 + c) * D1 + b) * L.nx + ex) * D1 + a;
 }
 
 // Trilinear Jacobian determinant at reference point (xi, et, ze) of the

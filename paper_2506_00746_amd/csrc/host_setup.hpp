@@ -31,10 +31,6 @@ struct Lattice {
   std::vector<uint8_t> interior;
 };
 
-// Position of entry (element e, local node a + D1 (b + D1 c)) in the output
-// E-vector (layout chosen by FEOD_EVEC_ROWMAJOR: e*Ne + local by default).
-int64_t evec_position(const Lattice& L, int64_t e, int local);
-
 // Returns false (with msg) when a size would overflow 32-bit indices.
 bool make_lattice(int nx, int ny, int nz, int k, Lattice* L, std::string* msg);
 

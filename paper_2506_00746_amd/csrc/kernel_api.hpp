@@ -64,16 +64,6 @@ struct ElemParams {
   FastDiv div_nx, div_ny;  // element index -> (ex, ey, ez)
 };
 
-// Output E-vector layout: 0 (default) = [e][c][b][a], each element's entries
-// contiguous, so the element kernel's writes are whole-element runs; 1 =
-// [ez][ey][c][b][ex][a], element rows contiguous per (c,b).  Measured on whole
-// Jacobian applies: 0 is faster on 32^3 Q3 (39-40 vs 42 us; the element
-// kernel's whole-element writes win), 1 by 3-4% on 64^3 Q4 and 48^3 Q2 (G^T
-// reads contiguous runs).
-#ifndef FEOD_EVEC_ROWMAJOR
-#define FEOD_EVEC_ROWMAJOR 0
-#endif
-
 // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
 // L2).  Renumber them so that XCD j processes one contiguous range of the
 // logical batches: neighbouring elements (and DOFs) then share an L2.

@@ -88,12 +88,8 @@ __device__ __forceinline__ void lattice_row_sum(const LatticeDims& d, const TE* 
       const bool use = (tx || lx) && (ty || ly) && (tz || lz);
       const int ex = ix - 1 + tx, ey = iy - 1 + ty, ez = iz - 1 + tz;
       const int a = I - k * ex, b = J - k * ey, c = K - k * ez;
-#if FEOD_EVEC_ROWMAJOR
-      const uint32_t j = ((((uint32_t)ez * d.ny + ey) * D1 + c) * D1 + b) * (uint32_t)(d.nx * D1) + ex * D1 + a;
-#else
       const uint32_t j = ((uint32_t)ex + (uint32_t)d.nx * (ey + (uint32_t)d.ny * ez)) * (uint32_t)(D1 * D1 * D1) +
                          a + D1 * (b + D1 * c);
-#endif
       v0[q] = use ? Y0[j] : TE(0);
       if (TWO) v1[q] = use ? Y1[j] : TE(0);
     }

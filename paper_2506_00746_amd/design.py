@@ -19,20 +19,24 @@ class DesignSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, rho: torch.Tensor, problem: Problem, opts: dict | None = None):
         opts = dict(opts or {})
-        problem.set_rho(rho)
+        rho64 = rho.detach().to(device=problem.device, dtype=torch.float64).contiguous().clone()
+        problem.set_rho(rho64)
         u, rep = problem.newton_solve(None, **opts)
         ctx.problem = problem
         ctx.opts = opts
         ctx.report = rep
         ctx.rho_meta = (rho.dtype, rho.device)
-        ctx.save_for_backward(u)
+        # the problem's coefficient may be changed before backward runs (another
+        # apply, set_rho): the gradient is taken at this call's rho
+        ctx.save_for_backward(u, rho64)
         return u
 
     @staticmethod
     def backward(ctx, grad_u: torch.Tensor):
-        (u,) = ctx.saved_tensors
+        u, rho64 = ctx.saved_tensors
         opts = {k: v for k, v in ctx.opts.items()
                 if k in ("rtol", "max_cg", "check_every", "prec", "jacobi", "partial_assembly")}
+        ctx.problem.set_rho(rho64)
         g_u = grad_u.to(device=u.device, dtype=torch.float64).contiguous()
         grad_rho, _, _ = ctx.problem.adjoint_gradient(u, g_u, **opts)
         dtype, device = ctx.rho_meta

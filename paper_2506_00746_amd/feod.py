@@ -78,7 +78,7 @@ _SIGS = {
     "feod_set_tangent_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
-    "feod_energy": (ctypes.c_int, [_P, _P, _P]),
+    "feod_energy": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_pa_setup": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "feod_jacobian_apply_pa": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_element_tangents": (ctypes.c_int, [_P, _P, ctypes.c_int64, ctypes.c_int64, _P]),
@@ -296,10 +296,10 @@ class Problem:
                self._ctx)
         return out
 
-    def energy(self, u):
+    def energy(self, u, prec="fp64"):
         e = torch.empty(1, dtype=torch.float64, device=self.device)
         self._sync_stream()
-        _check(lib().feod_energy(self._ctx, self._ptr(u, self.n_dofs, "u"), e.data_ptr()), self._ctx)
+        _check(lib().feod_energy(self._ctx, self._ptr(u, self.n_dofs, "u"), e.data_ptr(), PREC[prec]), self._ctx)
         return e
 
     def jacobian_diagonal(self, u, out=None, prec="fp64"):

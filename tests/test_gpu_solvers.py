@@ -98,7 +98,7 @@ def test_jacobi_preconditioned_newton_and_adjoint(prec):
     w = Workload("pcg", 6, 5, 4, 3, 5, 4.0, 1e-3, 33, perturb=True, rho=True)
     announce("jacobi pcg", w, prec)
     prob, ora, _ = setup(w)
-    u1, rep1 = prob.newton_solve(rtol=1e-12, prec=prec)
+    u1, rep1 = prob.newton_solve(rtol=1e-12, prec=prec, jacobi=0)
     u2, rep2 = prob.newton_solve(rtol=1e-12, prec=prec, jacobi=1)
     print("CG iterations plain", rep1["cg_iters_total"], "jacobi", rep2["cg_iters_total"])
     assert rep2["status"] == 0 and rep2["res_final"] <= 1e-12 * rep2["ref_norm"]
@@ -106,7 +106,7 @@ def test_jacobi_preconditioned_newton_and_adjoint(prec):
     u_o, _ = newton(ora, tol=1e-13)
     assert relerr(host(u2), u_o) <= 1e-10
     b = dev(ora.b)
-    g1, _, r1 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec)
+    g1, _, r1 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec, jacobi=0)
     g2, _, r2 = prob.adjoint_gradient(u2, b, rtol=1e-12, prec=prec, jacobi=1)
     assert relerr(host(g2), host(g1)) <= 1e-9
 
@@ -154,3 +154,112 @@ def test_binding_argument_handling():
     # an empty element range is a no-op for both tangent variants
     for method in ("res", "elm"):
         assert prob.element_tangents(u, first=3, count=0, method=method).shape == (0, ne, ne)
+
+
+def test_design_solve_backward_uses_its_own_rho():
+    """Two DesignSolve applies with different rho on one Problem before either
+    backward: each gradient is the one taken at its own rho (the adjoint
+    paragraph after Eq. (3)), equal to a single apply's gradient."""
+    w = Workload("two-rho", 4, 3, 3, 2, 3, 3.0, 1e-2, 35, perturb=True, rho=True)
+    announce("design solve two applies", w)
+    prob, ora, inp = setup(w)
+    b = dev(ora.b)
+    rho_a = torch.as_tensor(inp["rho"], device="cuda:0")
+    rho_b = torch.as_tensor(np.random.default_rng(36).uniform(0.1, 1.0, ora.E), device="cuda:0")
+    opts = {"rtol": 1e-13}
+
+    def single(r):
+        x = r.clone().requires_grad_(True)
+        torch.dot(b, feod.DesignSolve.apply(x, prob, opts)).backward()
+        return x.grad.clone()
+
+    ga, gb = single(rho_a), single(rho_b)
+    assert relerr(host(ga), host(gb)) > 1e-3  # the two coefficients give different gradients
+    xa = rho_a.clone().requires_grad_(True)
+    xb = rho_b.clone().requires_grad_(True)
+    phi_a = torch.dot(b, feod.DesignSolve.apply(xa, prob, opts))
+    phi_b = torch.dot(b, feod.DesignSolve.apply(xb, prob, opts))
+    phi_a.backward()
+    phi_b.backward()
+    assert relerr(host(xa.grad), host(ga)) <= 1e-10
+    assert relerr(host(xb.grad), host(gb)) <= 1e-10
+    # against the oracle's adjoint gradient at rho_a
+    ora_a = Discretisation(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=inp["vertices"],
+                           rho=inp["rho"])
+    u_o, _ = newton(ora_a, tol=1e-13)
+    _, g_o = adjoint(ora_a, u_o, ora_a.b)
+    assert relerr(host(xa.grad), g_o) <= 1e-9
+
+
+@pytest.mark.parametrize("name", ["c2", "c4"])
+def test_full_size_newton_certified_by_oracle_residual(name):
+    """The 32^3 Q3 (p = 4, eps = 1e-3) and 48^3 Q2 design (p = 3, rho) Newton
+    solutions in FP64 and mixed precision, certified by the oracle's own
+    residual: ||R_oracle(u_gpu)||_2 <= 1e-10 ||M b||_2 (Eq. (1)), and the two
+    precisions within 1e-9 of each other."""
+    w = WORKLOADS[name]
+    announce("full-size Newton certification", name)
+    prob, ora, inp = setup(w)
+    ref = np.linalg.norm(ora.mask * ora.b)
+    sols = {}
+    for prec in ("fp64", "mixed"):
+        u, rep = prob.newton_solve(rtol=1e-10, prec=prec)
+        assert rep["status"] == 0, rep
+        uh = host(u)
+        cert = np.linalg.norm(ora.residual(uh)) / ref
+        print(f"[{name}] {prec}: Newton {rep['newton_iters']} steps, {rep['cg_iters_total']} CG iterations, "
+              f"GPU rel. residual {rep['res_final'] / rep['ref_norm']:.2e}, oracle rel. residual {cert:.2e}")
+        assert cert <= 1e-10
+        sols[prec] = uh
+    assert relerr(sols["mixed"], sols["fp64"]) <= 1e-9
+    del prob
+    torch.cuda.empty_cache()
+
+
+def test_curved_q7_adjoint_gradient_c5():
+    """16^3 Q7 curved workload: the adjoint design gradient at rho = 1 in FP64
+    and mixed precision (the adjoint paragraph after Eq. (3)) against central
+    finite differences of Phi = b^T u on seeded elements, and the gradient
+    kernel against the oracle on those elements for the same u and lambda."""
+    w = WORKLOADS["c5"]
+    announce("adjoint c5")
+    prob, ora, inp = setup(w, compute_load=False)
+    b = dev(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq, vertices=inp["vertices"]).load)
+    u, rep = prob.newton_solve(rtol=1e-13)
+    assert rep["status"] == 0, rep
+    grads = {}
+    for prec in ("fp64", "mixed"):
+        g, lam, arep = prob.adjoint_gradient(u, b, rtol=1e-12, prec=prec)
+        assert arep["status"] == 0, arep
+        grads[prec] = (host(g), host(lam))
+        print(f"[c5] adjoint {prec}: {arep['cg_iters_total']} CG iterations, "
+              f"{arep['refine_iters']} reliable updates, rel. residual {arep['res_final'] / arep['ref_norm']:.2e}")
+    g64, lam64 = grads["fp64"]
+    e_mixed = relerr(grads["mixed"][0], g64)
+    print(f"[c5] mixed vs FP64 adjoint gradient: {e_mixed:.2e}")
+    assert e_mixed <= 1e-9
+    elems = np.sort(np.random.default_rng(505).choice(w.n_elems, 6, replace=False))
+    # gradient kernel vs the oracle at the same u, lambda (sampled elements)
+    g_o = ora.grad_rho(host(u), lam64, elems)[elems]
+    assert relerr(g64[elems], g_o) <= 1e-12
+    gk32 = host(prob.grad_rho(u, dev(lam64), prec="mixed"))
+    print(f"[c5] FP32 gradient kernel rel. error on sampled elements: {relerr(gk32[elems], g_o):.2e}")
+    assert relerr(gk32[elems], g_o) <= 5e-6
+    # central differences of Phi(rho) = b^T u(rho), rho_e = 1 -+ 1e-3
+    u0 = u.clone()
+    worst = 0.0
+    for e in elems:
+        phis = []
+        for s in (1.0, -1.0):
+            r = torch.ones(w.n_elems, dtype=torch.float64, device="cuda:0")
+            r[int(e)] += s * 1e-3
+            prob.set_rho(r)
+            us, rp = prob.newton_solve(u0, init_poisson=0, rtol=1e-13)
+            assert rp["status"] == 0, rp
+            phis.append(float(torch.dot(b, us)))
+        fd = (phis[0] - phis[1]) / 2e-3
+        worst = max(worst, abs(fd - g64[e]) / abs(g64[e]))
+    print(f"[c5] worst relative FD mismatch over {len(elems)} elements: {worst:.2e}")
+    assert worst <= 1e-5
+    del prob
+    torch.cuda.empty_cache()
