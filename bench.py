@@ -3,7 +3,10 @@
 One step = one Jacobian-vector apply J(u) v (G -> B -> dual-number D -> B^T ->
 G^T) in FP64 on the workload's seeded random u, v, with the inputs already
 resident in HBM.  value = n_dofs * steps / elapsed / 1e9 (GDOF/s) on the
-32^3 Q3 p = 4 workload (c2).
+64^3 Q4 p = 2.5 workload (16,974,593 DOFs), the largest of the five and the
+one the FP64-vs-mixed throughput comparison is made on.  The same K steps are
+timed again in --repeats further windows; their median is reported beside
+value.
 
 Also reported on the same JSON line (each timed separately, none of it part
 of ``value``): the mixed-precision Jacobian apply, the residual, the fused
@@ -20,8 +23,9 @@ Before the W warm-up steps the apply runs untimed for --settle seconds (0.5 by
 default): an idle GPU raises its clocks during the first milliseconds of work,
 and the K timed steps measure the steady state.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2]
-       [--settle S] [--no-extras] [--no-cpu-baseline] [--calibrate-copy]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
+       [--settle S] [--repeats R] [--no-extras] [--no-cpu-baseline]
+       [--calibrate-copy] [--cpu-table]
 """
 from __future__ import annotations
 
@@ -31,13 +35,16 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "GDOF/s of AD Jacobian-vector apply (FP64 vs mixed) + adjoint-gradient time"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 FP64_PEAK_TFS = 78.6           # 256 CU * 2.4 GHz * 128 FLOP/clk (vector FP64 FMA)
-FP32_PEAK_TFS = 78.6           # non-packed FP32 FMA: same lane rate as FP64
+FP32_PEAK_TFS = 78.6           # non-packed FP32 FMA (packed FP32 is compiled out): same lane rate as FP64
+FP32_PUBLISHED_TFS = 157.3     # MI355X's published FP32 vector peak (packed FP32), reported beside
 
 
 def log(*a):
@@ -126,6 +133,8 @@ def roofline(prob, op, prec, stats, kernel, kernel_ms=None):
     r.update({"kernel": kernel, "avg_us": avg_s * 1e6, "algorithmic_bytes": bytes_,
               "algorithmic_flops": flops, "achieved_GBs": gbs, "achieved_TFLOPs": tfs,
               "traffic": None})
+    if prec != "fp64":
+        r["frac_vs_published_fp32"] = tfs / FP32_PUBLISHED_TFS
     return r
 
 
@@ -152,6 +161,7 @@ def apply_rows(prob, u, v, w, args, only=None):
         gt = st.get("gather_transpose", st.get("gather_transpose2", {"avg_ms": 0.0}))
         out[name] = {"GDOF/s": N / (t * 1e-3) / 1e9, "us_per_apply": t * 1e3, "kernel_us": rl["avg_us"],
                      "kernel_bound": rl["bound"], "kernel_frac": rl["frac"],
+                     "kernel_frac_vs_published_fp32": rl.get("frac_vs_published_fp32"),
                      "kernel_TFLOPs": rl["achieved_TFLOPs"], "kernel_GBs": rl["achieved_GBs"],
                      "gather_t_us": gt["avg_ms"] * 1e3, "roofline": rl}
     if "jvp_fp64" in out and "jvp_mixed" in out:
@@ -159,54 +169,84 @@ def apply_rows(prob, u, v, w, args, only=None):
     return out
 
 
-def solve_rows(feod, WORKLOADS, make_inputs, dev):
-    """Newton-CG and adjoint-gradient wall times (synchronised) on the design
-    workload (c4) and the 32^3 Q3 workload (c2): FP64 vs mixed, with and
-    without partial assembly inside CG and Jacobi preconditioning."""
+def _newton_row(pb, torch, **opts):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    u, rep = pb.newton_solve(rtol=1e-10, **opts)
+    torch.cuda.synchronize()
+    return u, {"ms": (time.perf_counter() - t0) * 1e3, "newton_iters": rep["newton_iters"],
+               "cg_iters": rep["cg_iters_total"], "res_final_rel": rep["res_final"] / rep["ref_norm"],
+               "status": rep["status"]}
+
+
+def _adjoint_row(pb, torch, u, b, **opts):
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g, lam, rep = pb.adjoint_gradient(u, b, rtol=1e-10, **opts)
+    torch.cuda.synchronize()
+    row = {"ms": (time.perf_counter() - t0) * 1e3, "cg_iters": rep["cg_iters_total"],
+           "refine_iters": rep["refine_iters"], "res_final_rel": rep["res_final"] / rep["ref_norm"],
+           "status": rep["status"]}
+    # the same solve again with every launch timed by events: GPU kernel time
+    pb.profile(True)
+    pb.adjoint_gradient(u, b, rtol=1e-10, **opts)
+    row["kernel_sum_ms"] = sum(ms for _, ms in pb.profile_read().values())
+    pb.profile(False)
+    return g, row
+
+
+def solve_rows(feod, WORKLOADS, make_inputs, dev, names=("c3", "c4", "c2", "c5")):
+    """Newton-CG and adjoint-gradient wall times (synchronised).  Every solve
+    stops at the same FP64 relative residual 1e-10 (the residual is FP64 in
+    both precisions), so FP64 and mixed are compared at equal final accuracy.
+    64^3 Q4: FP64 vs mixed (the solver defaults: fused Jacobian action, Jacobi).
+    48^3 Q2 and 32^3 Q3: also with partial assembly and without Jacobi.
+    48^3 Q2 and 16^3 Q7 curved: the adjoint design gradient (compliance) in
+    FP64 and mixed, and the gradient kernel alone in FP64 and FP32."""
     import torch
     out = {}
-    for name in ("c4", "c2"):
+    for name in names:
         w = WORKLOADS[name]
         ii = make_inputs(w)
-        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, rho=ii["rho"], device=dev)
-        b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load, device=dev)
+        pb = feod.Problem(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=ii["vertices"], rho=ii["rho"],
+                          device=dev)
+        b = torch.as_tensor(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq, vertices=ii["vertices"]).load,
+                            device=dev)
+        combos = [(0, 1)] if name in ("c3", "c5") else [(pa, jac) for pa in (0, 1) for jac in (0, 1)]
         u_ref = None
+        t_ref = {}
         for prec in ("fp64", "mixed"):
-            for pa in (0, 1):
-                for jac in (0, 1):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    u, rep = pb.newton_solve(rtol=1e-10, prec=prec, partial_assembly=pa, jacobi=jac)
-                    torch.cuda.synchronize()
-                    row = {"ms": (time.perf_counter() - t0) * 1e3, "newton_iters": rep["newton_iters"],
-                           "cg_iters": rep["cg_iters_total"], "res_final_rel": rep["res_final"] / rep["ref_norm"]}
-                    if u_ref is None:
-                        u_ref = u.clone()
-                    else:
-                        row["u_rel_diff_vs_fp64"] = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
-                    out[f"{name}_newton_{prec}_pa{pa}_jacobi{jac}"] = row
-        if name == "c4":
+            for pa, jac in combos:
+                u, row = _newton_row(pb, torch, prec=prec, partial_assembly=pa, jacobi=jac)
+                if u_ref is None:
+                    u_ref = u.clone()
+                else:
+                    row["u_rel_diff_vs_fp64"] = float(torch.linalg.norm(u - u_ref) / torch.linalg.norm(u_ref))
+                if prec == "fp64":
+                    t_ref[(pa, jac)] = row["ms"]
+                else:
+                    row["speedup_vs_fp64_at_equal_residual"] = t_ref[(pa, jac)] / row["ms"]
+                out[f"{name}_newton_{prec}_pa{pa}_jacobi{jac}"] = row
+        if name in ("c4", "c5"):
             g_ref = None
             for prec in ("fp64", "mixed"):
-                for pa in (0, 1):
-                    torch.cuda.synchronize()
-                    t0 = time.perf_counter()
-                    g, lam, rep = pb.adjoint_gradient(u_ref, b, rtol=1e-10, prec=prec, partial_assembly=pa)
-                    torch.cuda.synchronize()
-                    row = {"ms": (time.perf_counter() - t0) * 1e3, "cg_iters": rep["cg_iters_total"],
-                           "refine_iters": rep["refine_iters"],
-                           "res_final_rel": rep["res_final"] / rep["ref_norm"]}
+                for pa in ((0, 1) if name == "c4" else (0,)):
+                    g, row = _adjoint_row(pb, torch, u_ref, b, prec=prec, partial_assembly=pa)
                     if g_ref is None:
                         g_ref = g.clone()
                     else:
                         row["grad_rel_diff_vs_fp64"] = float(torch.linalg.norm(g - g_ref) / torch.linalg.norm(g_ref))
-                    # the same solve again with every launch timed by events: GPU kernel time
-                    pb.profile(True)
-                    pb.adjoint_gradient(u_ref, b, rtol=1e-10, prec=prec, partial_assembly=pa)
-                    row["kernel_sum_ms"] = sum(ms for _, ms in pb.profile_read().values())
-                    pb.profile(False)
-                    out[f"c4_adjoint_gradient_{prec}_pa{pa}"] = row
-        del pb
+                    out[f"{name}_adjoint_gradient_{prec}_pa{pa}"] = row
+            # the gradient kernel alone at (u, lambda = u): FP64 vs FP32
+            g64 = pb.grad_rho(u_ref, u_ref)
+            krow = {}
+            for prec in ("fp64", "mixed"):
+                ms = timed_loop(lambda: pb.grad_rho(u_ref, u_ref, prec=prec), 50, 5)
+                gk = pb.grad_rho(u_ref, u_ref, prec=prec)
+                krow[prec] = {"us": ms * 1e3,
+                              "rel_err_vs_fp64": float(torch.linalg.norm(gk - g64) / torch.linalg.norm(g64))}
+            out[f"{name}_grad_kernel"] = krow
+        del pb, b, u_ref
         torch.cuda.empty_cache()
     for k, v in out.items():
         log(f"[bench] solve {k}: {v}")
@@ -366,23 +406,62 @@ def mixed_error_rows(feod, WORKLOADS, make_inputs, dev):
     return out
 
 
-def cpu_baseline(w, inp, budget_s=12.0):
-    """The oracle's Jacobian apply on the same workload, timed on host cores."""
+def cpu_baseline(w, inp, budget_s=12.0, chunk=2048):
+    """The oracle's Jacobian apply on the same workload, timed on host cores
+    over a bounded sample: whole chunks of consecutive elements, as many as
+    the time budget allows (at least one), scaled to GDOF/s of a full apply
+    (N DOFs per E elements)."""
     import threadpoolctl
     from oracle import Discretisation
     d = Discretisation(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=inp["vertices"],
-                       rho=inp["rho"], compute_load=False)
+                       rho=inp["rho"], compute_load=False, chunk=chunk)
     threads = max([x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()] + [1])
-    n, t0 = 0, time.perf_counter()
-    while True:
-        d.jvp(inp["u"], inp["v"])
-        n += 1
+    n_el, t0 = 0, time.perf_counter()
+    while n_el < w.n_elems:
+        elems = (n_el + np.arange(min(chunk, w.n_elems - n_el)))
+        d.jvp(inp["u"], inp["v"], elems)
+        n_el += elems.size
         el = time.perf_counter() - t0
-        if el >= budget_s or n >= 5:
+        if el >= budget_s:
             break
-    return {"value": w.n_dofs * n / el / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} full Jacobian applies of the {w.name} workload ({el:.1f} s, "
-                      f"dense-element NumPy/OpenBLAS, {os.cpu_count()} host CPUs visible)"}
+    full_s = el * w.n_elems / n_el
+    return {"value": w.n_dofs / full_s / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle Jacobian apply over {n_el} of the {w.n_elems} elements of the {w.name} "
+                      f"workload in {el:.1f} s (dense-element NumPy/OpenBLAS, {os.cpu_count()} host CPUs "
+                      f"visible), scaled to a full apply of {w.n_dofs} DOFs ({full_s:.1f} s)"}
+
+
+def cpu_table(WORKLOADS, make_inputs):
+    """The oracle's residual and Jacobian apply on every workload, full
+    applies, median of 3, and its Newton solve on the 4^3 Q2 workload."""
+    import threadpoolctl
+    from oracle import Discretisation, newton
+    threads = max([x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()] + [1])
+    out = {"cores": threads}
+    for name in ("c1", "c2", "c3", "c4", "c5"):
+        w = WORKLOADS[name]
+        inp = make_inputs(w)
+        d = Discretisation(w.nx, w.ny, w.nz, w.k, w.nq, w.p, w.eps, vertices=inp["vertices"],
+                           rho=inp["rho"], compute_load=(name == "c1"))
+        if d.b is None:
+            d.b = np.zeros(d.N)  # the load is a subtraction; its cost is not the apply's
+        row = {}
+        for op, fn in (("residual", lambda: d.residual(inp["u"])), ("jvp", lambda: d.jvp(inp["u"], inp["v"]))):
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+            med = sorted(ts)[1]
+            row[op] = {"s": med, "GDOF/s": w.n_dofs / med / 1e9}
+        if name == "c1":
+            t0 = time.perf_counter()
+            newton(d, tol=1e-10)
+            row["newton_s"] = time.perf_counter() - t0
+        out[name] = row
+        log(f"[bench] oracle {name}: {row}")
+        del d
+    return out
 
 
 def main():
@@ -390,9 +469,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--workload", default="c3")
     ap.add_argument("--settle", type=float, default=0.5,
                     help="seconds of untimed applies before the warm-up steps (GPU clocks reach steady state)")
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="further windows of K timed steps; their median is reported beside value")
+    ap.add_argument("--cpu-table", action="store_true",
+                    help="also time the oracle's full residual and Jacobian applies on every workload "
+                         "(median of 3; minutes of CPU time)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -436,11 +520,16 @@ def main():
     k_ms = element_kernel_ms(prob, u, v, "jvp", "fp64", args.steps, args.warmup)
     roof = roofline(prob, "jvp", "fp64", stats, "element_jvp_f64", kernel_ms=k_ms)
     roof["traffic"] = stored_traffic(w.name, "element_jvp_f64")
-    log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s; element kernel {k_ms * 1e3:.2f} us "
-        f"back-to-back; per-launch events {stats}")
+    reps = sorted(timed_loop(jvp64, args.steps, 0) for _ in range(args.repeats))
+    rep_med = reps[len(reps) // 2] if reps else ms
+    log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s (median of {len(reps)} more windows "
+        f"{rep_med * 1e3:.1f} us); element kernel {k_ms * 1e3:.2f} us back-to-back; per-launch events {stats}")
 
     rows = {w.name: {"jvp_fp64": {"GDOF/s": value, "us_per_apply": ms * 1e3, "kernel_us": roof["avg_us"],
-                                  "kernel_bound": roof["bound"], "kernel_frac": roof["frac"]}}}
+                                  "kernel_bound": roof["bound"], "kernel_frac": roof["frac"],
+                                  "repeat_windows_us": [t * 1e3 for t in reps],
+                                  "repeat_median_GDOF/s": N / (rep_med * 1e-3) / 1e9,
+                                  "gather_t_us": stats.get("gather_transpose", {"avg_ms": 0.0})["avg_ms"] * 1e3}}}
     if not args.no_extras:
         rows[w.name].update(apply_rows(prob, u, v, w, args,
                                        only=("jvp_mixed", "residual_fp64", "residual_jvp_fp64")))
@@ -473,6 +562,8 @@ def main():
         log("[bench] CPU oracle baseline ...")
         cpu = cpu_baseline(w, inp)
         log(f"[bench] cpu_baseline {cpu}")
+    if args.cpu_table:
+        rows["oracle_table"] = cpu_table(WORKLOADS, make_inputs)
 
     out = {"metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",

@@ -27,3 +27,15 @@ def test_tangent_flop_count_formula():
     assert bench.tangent_flops_per_element(3, 5) == (12 * nq ** 3 * d1 ** 3 + 150 * nq ** 3
                                                      + 27 * (nq ** 3 * d1 ** 2 + nq ** 2 * d1 ** 4)
                                                      + 12 * nq * d1 ** 6)
+
+
+def test_cpu_baseline_sample_is_scaled_to_a_full_apply():
+    """The oracle leg times whole chunks of elements and scales to one full
+    apply: on the 4^3 Q2 workload with a zero budget it takes one chunk."""
+    sys.path.insert(0, ROOT)
+    import bench
+    from workloads import WORKLOADS, make_inputs
+    w = WORKLOADS["c1"]
+    r = bench.cpu_baseline(w, make_inputs(w), budget_s=0.0, chunk=16)
+    assert r["kind"] == "oracle" and r["unit"] == "GDOF/s" and r["value"] > 0 and r["cores"] >= 1
+    assert "over 16 of the 64 elements" in r["sample"]
