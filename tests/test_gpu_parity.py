@@ -355,7 +355,7 @@ def test_eps0_zero_gradient(w):
     announce("eps = 0 zero gradient", w)
     prob, ora, inp = setup(w)
     N = ora.N
-    bm = ora.mask * feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq).load
+    bm = ora.mask * feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq, vertices=inp["vertices"]).load
     z = dev(np.zeros(N))
     v = dev(inp["v"])
     for prec in ("fp64", "mixed"):

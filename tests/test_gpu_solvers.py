@@ -225,7 +225,9 @@ def test_curved_q7_adjoint_gradient_c5():
     announce("adjoint c5")
     prob, ora, inp = setup(w, compute_load=False)
     b = dev(feod.HostSetup(w.nx, w.ny, w.nz, w.k, w.nq, vertices=inp["vertices"]).load)
-    u, rep = prob.newton_solve(rtol=1e-13)
+    # the FP64 residual of this workload has a floor near 2.6e-13 relative (one
+    # ulp of u moves it by that much), so the solves stop at 1e-12
+    u, rep = prob.newton_solve(rtol=1e-12)
     assert rep["status"] == 0, rep
     grads = {}
     for prec in ("fp64", "mixed"):
@@ -254,7 +256,7 @@ def test_curved_q7_adjoint_gradient_c5():
             r = torch.ones(w.n_elems, dtype=torch.float64, device="cuda:0")
             r[int(e)] += s * 1e-3
             prob.set_rho(r)
-            us, rp = prob.newton_solve(u0, init_poisson=0, rtol=1e-13)
+            us, rp = prob.newton_solve(u0, init_poisson=0, rtol=1e-12)
             assert rp["status"] == 0, rp
             phis.append(float(torch.dot(b, us)))
         fd = (phis[0] - phis[1]) / 2e-3
