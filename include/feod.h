@@ -182,6 +182,22 @@ feod_status feod_residual(feod_ctx* ctx, const double* u, double* r, feod_prec p
 feod_status feod_jacobian_apply(feod_ctx* ctx, const double* u, const double* v,
                                 double* jv, double* r_or_null, feod_prec prec);
 
+/* For callers that cannot allocate device memory per call (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation): the
+ * Jacobian action of feod_jacobian_apply (no residual) with the E-vector
+ * between the element stage and G^T held in a library-owned static device
+ * array of 32 MiB per GPU (looked up at feod_bind_workspace, kept until the
+ * process ends) instead of the context's workspace.  Calls no allocating
+ * routine.  Results are bitwise those of feod_jacobian_apply.  The
+ * E-vector takes nx*ny*nz*(k+1)^3 * 8 bytes (FP64) or * 4 (FEOD_MIXED);
+ * larger meshes return FEOD_EINVAL (use feod_jacobian_apply).  Every call on
+ * one GPU, from any context, shares that GPU's array: calls that overlap in
+ * time on one GPU (different streams or threads) race and must be ordered by
+ * the caller.  The context's bound workspace still provides the mesh data
+ * (coefficients, vertices, maps).  u, v, jv: device, length N. */
+feod_status feod_jacobian_apply_noalloc(feod_ctx* ctx, const double* u, const double* v,
+                                        double* jv, feod_prec prec);
+
 /* The element stage alone, G -> B -> D -> B^T of Eq. (1)/(2), written into
  * the context's internal E-vector(s) (no G^T): op 0 residual, 1 Jacobian
  * action, 2 both.  For timing the element kernel on its own; u, v: device,

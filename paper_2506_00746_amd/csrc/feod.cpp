@@ -13,6 +13,7 @@
 
 #include "host_setup.hpp"
 #include "kernel_api.hpp"
+#include "noalloc.hpp"
 
 using namespace feod;
 
@@ -578,6 +579,7 @@ feod_status feod_bind_workspace(feod_ctx* c, void* dev, size_t bytes) {
   if (bytes < l.total)
     return fail(c, FEOD_EINVAL, "workspace too small: need " + std::to_string(l.total) + " bytes");
   HIP_TRY(c, hipGetDevice(&c->device));
+  HIP_TRY(c, noalloc_init(c->device));  // the static scratch of feod_jacobian_apply_noalloc on this device
   char* w = (char*)dev;
   c->ws = w;
   c->ws_bytes = bytes;
@@ -680,6 +682,28 @@ feod_status feod_jacobian_apply(feod_ctx* c, const double* u, const double* v, d
   if (r && (overlap(u, nb, r, nb) || overlap(v, nb, r, nb) || overlap(jv, nb, r, nb)))
     return fail(c, FEOD_EINVAL, "r overlaps another argument");
   return apply_jvp(c, u, v, jv, r, prec == FEOD_MIXED);
+}
+
+feod_status feod_jacobian_apply_noalloc(feod_ctx* c, const double* u, const double* v, double* jv,
+                                        feod_prec prec) {
+  if (!c) return fail(nullptr, FEOD_EINVAL, "null context");
+  TRY(check_prec(c, prec));
+  const int pr = prec == FEOD_MIXED;
+  const size_t need = (size_t)c->lat.E * c->Ne * (pr ? 4 : 8);
+  if (need > kNoallocScratchBytes)
+    return fail(c, FEOD_EINVAL,
+                "the E-vector needs " + std::to_string(need) + " bytes, more than the " +
+                    std::to_string(kNoallocScratchBytes) + "-byte static scratch: use feod_jacobian_apply");
+  TRY(need_bound(c));
+  TRY(check_vec(c, u, "u"));
+  TRY(check_vec(c, v, "v"));
+  TRY(check_vec(c, jv, "jv"));
+  const size_t nb = (size_t)c->lat.N * 8;
+  if (overlap(u, nb, jv, nb) || overlap(v, nb, jv, nb)) return fail(c, FEOD_EINVAL, "jv overlaps an input");
+  void* Y = noalloc_scratch(c->device);
+  if (!Y) return fail(c, FEOD_ESTATE, "static scratch not set up on the context's device");
+  TRY(run_element(c, OP_JVP, pr, params(c, u, v, Y, nullptr, pr)));
+  return timed(c, "gather_transpose", [&] { return gather_t(c, Y, nullptr, pr == 1, nullptr, jv, nullptr); });
 }
 
 feod_status feod_element_vectors(feod_ctx* c, int32_t op, const double* u, const double* v, feod_prec prec) {

@@ -78,6 +78,7 @@ _SIGS = {
     "feod_set_tangent_mode": (ctypes.c_int, [_P, ctypes.c_int32]),
     "feod_residual": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_jacobian_apply": (ctypes.c_int, [_P, _P, _P, _P, _P, ctypes.c_int]),
+    "feod_jacobian_apply_noalloc": (ctypes.c_int, [_P, _P, _P, _P, ctypes.c_int]),
     "feod_energy": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
     "feod_pa_setup": (ctypes.c_int, [_P, _P, ctypes.c_int]),
     "feod_jacobian_apply_pa": (ctypes.c_int, [_P, _P, _P, ctypes.c_int]),
@@ -249,6 +250,16 @@ class Problem:
         self._sync_stream()
         _check(lib().feod_jacobian_apply(self._ctx, self._ptr(u, self.n_dofs, "u"),
                                          self._ptr(v, self.n_dofs, "v"), out.data_ptr(), rp, PREC[prec]),
+               self._ctx)
+        return out
+
+    def jacobian_apply_noalloc(self, u, v, out, prec="fp64"):
+        """J(u) v with the E-vector in the library's static scratch (no
+        allocation by the library; ``out`` must be given)."""
+        self._ptr(out, self.n_dofs, "out")
+        self._sync_stream()
+        _check(lib().feod_jacobian_apply_noalloc(self._ctx, self._ptr(u, self.n_dofs, "u"),
+                                                 self._ptr(v, self.n_dofs, "v"), out.data_ptr(), PREC[prec]),
                self._ctx)
         return out
 

@@ -145,3 +145,23 @@ def test_cost_model_matches_its_formula():
         be, fe = hs.cost[("elm", "fp64")]
         assert fe == pytest.approx(d1 ** 3 * flops, rel=1e-14), name
         assert be == pytest.approx(nbytes - 8.0 * n - 8.0 * e * d1 ** 3 + 8.0 * e * d1 ** 6, rel=1e-14), name
+
+
+def test_noalloc_apply_rejects_meshes_beyond_its_scratch():
+    """feod_jacobian_apply_noalloc holds the E-vector in a 32 MiB static
+    array: a 90^3 Q1 mesh (46.7 MB FP64 E-vector) is refused with
+    FEOD_EINVAL before any GPU work, while its FP32 E-vector (23.3 MB) fits
+    and the unbound context is then the error."""
+    L = feod.lib()
+    d = feod.feod.MeshDesc(90, 90, 90, 1, 2, 3.0, 1e-2, None, None, None, None)
+    ctx = ctypes.c_void_p()
+    assert L.feod_setup_mesh(ctypes.byref(d), ctypes.byref(ctx)) == 0
+    try:
+        assert L.feod_jacobian_apply_noalloc(ctx, 256, 512, 768, 0) == feod.feod.FEOD_EINVAL
+        msg = L.feod_last_error(ctx).decode()
+        assert "46656000" in msg and str(32 << 20) in msg
+        assert L.feod_jacobian_apply_noalloc(ctx, 256, 512, 768, 1) == feod.feod.FEOD_ESTATE
+        assert L.feod_jacobian_apply_noalloc(ctx, 256, 512, 768, 5) == feod.feod.FEOD_EINVAL
+    finally:
+        L.feod_destroy(ctx)
+    assert L.feod_jacobian_apply_noalloc(None, 256, 512, 768, 0) == feod.feod.FEOD_EINVAL
