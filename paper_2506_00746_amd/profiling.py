@@ -74,6 +74,54 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dic
     return out
 
 
+def counters(pmc_dir: str, kernel: str) -> dict:
+    """Every counter of one --pmc run, averaged over the dispatches of ``kernel``."""
+    names = set()
+    with open(_one(os.path.join(pmc_dir, "**", "*counter_collection.csv"))) as f:
+        for r in csv.DictReader(f):
+            names.add(r["Counter_Name"])
+    out = {}
+    for c in sorted(names):
+        vals = [v for n, g, v in counter_per_dispatch(pmc_dir, c) if re.search(kernel, n)]
+        if vals:
+            out[c] = (sum(vals) / len(vals), len(vals))
+    return out
+
+
+# Executed floating-point operations from the VALU instruction counters: each
+# counted instruction is one wavefront instruction over 64 lanes; an FMA
+# counts 2, add, multiply and transcendental 1.
+FLOP_WEIGHTS = {"FMA": 2, "ADD": 1, "MUL": 1, "TRANS": 1}
+
+
+def executed_flops(cnt: dict, width: str) -> float | None:
+    names = [f"SQ_INSTS_VALU_{k}_{width}" for k in FLOP_WEIGHTS]
+    if not all(n in cnt for n in names):
+        return None
+    return 64.0 * sum(FLOP_WEIGHTS[k] * cnt[f"SQ_INSTS_VALU_{k}_{width}"][0] for k in FLOP_WEIGHTS)
+
+
+def counter_lines(pmc_dirs: list[str], kernel: str) -> list[str]:
+    cnt = {}
+    for d in pmc_dirs:
+        cnt.update(counters(d, kernel))
+    if not cnt:
+        return []
+    lines = ["", f"## Counters of `{kernel}` per dispatch (--pmc, one run per counter group)", "",
+             "| counter | average per dispatch | dispatches |", "|---|---|---|"]
+    for c, (v, n) in sorted(cnt.items()):
+        lines.append(f"| {c} | {v:.6g} | {n} |")
+    derived = []
+    for width in ("F64", "F32"):
+        fl = executed_flops(cnt, width)
+        if fl is not None:
+            derived.append(f"executed_flops_{width.lower()}_per_launch: {fl:.6g}")
+    if derived:
+        lines += ["", "Executed FLOPs = 64 lanes x (2 FMA + ADD + MUL + TRANS) wavefront instructions:", ""]
+        lines += derived
+    return lines
+
+
 def summary(args) -> str:
     stats = kernel_stats(args.trace)
     t = traffic(args.fetch, args.write, args.kernel, args.copy_bytes)
@@ -91,6 +139,7 @@ def summary(args) -> str:
         x = t[k]
         lines.append(f"| {x['counter']} | {x['copy_kib']:.0f} for {args.copy_bytes} B | {x['factor']:.3f} | "
                      f"{x['kernel_kib']:.1f} ({x['dispatches']} dispatches) | {x['bytes']:.4g} |")
+    lines += counter_lines(args.pmc or [], args.kernel)
     lines += ["", f"traffic_bytes_per_launch: {t['bytes']:.6g}",
               f"kernel_source_sha256: {kernel_source_sha256()}", ""]
     return "\n".join(lines)
@@ -116,6 +165,7 @@ def main():
     ap.add_argument("--copy-bytes", type=int, default=256 * 1024 * 1024)
     ap.add_argument("--title", default="")
     ap.add_argument("--cmd", action="append", dest="cmd_lines", default=[])
+    ap.add_argument("--pmc", action="append", default=[], help="directory of a further --pmc run (repeatable)")
     args = ap.parse_args()
     if args.what == "sha":
         print(kernel_source_sha256())
