@@ -154,6 +154,7 @@ def apply_rows(prob, u, v, w, args, only=None):
     for name, fn, op, prec, kern in cases:
         if only is not None and name not in only:
             continue
+        settle(fn, min(args.settle, 0.2))
         t = timed_loop(fn, args.steps, args.warmup)
         st = kernel_profile(prob, fn, min(args.steps, 50))
         k_ms = element_kernel_ms(prob, u, v, op, prec, args.steps, args.warmup)
@@ -370,9 +371,14 @@ def mall_cold_rows(feod, WORKLOADS, make_inputs, dev, reps=21):
         cold = sorted(times)[len(times) // 2]
         kbytes, _ = pb.kernel_cost("jvp", "fp64")
         nbytes = kbytes + 8 * w.n_elems * (w.k + 1) ** 3 + 8 * w.n_dofs
+        # the design's own byte count (u, v, G map, E-vector written and read,
+        # G^T map, L-vector written, curved vertices): 28 N + 24 E (k+1)^3 [+ 192 E]
+        sbytes = 28 * w.n_dofs + 24 * w.n_elems * (w.k + 1) ** 3 + (192 * w.n_elems if w.perturb else 0)
         out[name] = {"cold_us": cold * 1e3, "warm_us": warm * 1e3, "GDOF/s_cold": w.n_dofs / (cold * 1e-3) / 1e9,
                      "apply_bytes": nbytes, "hbm_frac_cold": nbytes / (cold * 1e-3) / (HBM_PEAK_GBS * 1e9),
-                     "copy_frac_cold": nbytes / (cold * 1e-3) / (copy_gbs * 1e9)}
+                     "copy_frac_cold": nbytes / (cold * 1e-3) / (copy_gbs * 1e9),
+                     "design_bytes": sbytes,
+                     "hbm_frac_cold_design_bytes": sbytes / (cold * 1e-3) / (HBM_PEAK_GBS * 1e9)}
         log(f"[bench] MALL-cold {name}: {out[name]}")
         del pb, u, v, jv
         torch.cuda.empty_cache()
@@ -433,7 +439,8 @@ def cpu_baseline(w, inp, budget_s=12.0, chunk=2048):
 
 def cpu_table(WORKLOADS, make_inputs):
     """The oracle's residual and Jacobian apply on every workload, full
-    applies, median of 3, and its Newton solve on the 4^3 Q2 workload."""
+    applies, median of 3 (one run on the 64^3 Q4 workload, about a minute per
+    apply), and its Newton solve on the 4^3 Q2 workload."""
     import threadpoolctl
     from oracle import Discretisation, newton
     threads = max([x.get("num_threads", 1) for x in threadpoolctl.threadpool_info()] + [1])
@@ -448,12 +455,12 @@ def cpu_table(WORKLOADS, make_inputs):
         row = {}
         for op, fn in (("residual", lambda: d.residual(inp["u"])), ("jvp", lambda: d.jvp(inp["u"], inp["v"]))):
             ts = []
-            for _ in range(3):
+            for _ in range(1 if name == "c3" else 3):
                 t0 = time.perf_counter()
                 fn()
                 ts.append(time.perf_counter() - t0)
-            med = sorted(ts)[1]
-            row[op] = {"s": med, "GDOF/s": w.n_dofs / med / 1e9}
+            med = sorted(ts)[len(ts) // 2]
+            row[op] = {"s": med, "GDOF/s": w.n_dofs / med / 1e9, "runs": len(ts)}
         if name == "c1":
             t0 = time.perf_counter()
             newton(d, tol=1e-10)
@@ -461,6 +468,43 @@ def cpu_table(WORKLOADS, make_inputs):
         out[name] = row
         log(f"[bench] oracle {name}: {row}")
         del d
+    return out
+
+
+def summary(rows):
+    """The headline figures of every row, in one short object (the JSON line
+    leads with it, ahead of the full rows)."""
+    out = {"jvp_GDOF/s": {}, "element_kernel_frac": {}, "newton_ms": {}, "adjoint_gradient_ms": {}}
+    for w in ("c3", "c2", "c4", "c5"):
+        r = rows.get(w, {})
+        for prec in ("fp64", "mixed"):
+            x = r.get(f"jvp_{prec}")
+            if x:
+                out["jvp_GDOF/s"][f"{w}_{prec}"] = round(x["GDOF/s"], 3)
+                out["element_kernel_frac"][f"{w}_{prec}"] = round(x["kernel_frac"], 4)
+                if prec == "mixed" and x.get("kernel_frac_vs_published_fp32") is not None:
+                    out["element_kernel_frac"][f"{w}_mixed_vs_published_fp32"] = round(
+                        x["kernel_frac_vs_published_fp32"], 4)
+        if r.get("jvp_mixed") and r.get("jvp_fp64"):
+            out["jvp_GDOF/s"][f"{w}_mixed_speedup"] = round(r["jvp_mixed"]["GDOF/s"] / r["jvp_fp64"]["GDOF/s"], 3)
+    sol = rows.get("solves", {})
+    for w in ("c3", "c2", "c4", "c5"):
+        a, b = sol.get(f"{w}_newton_fp64_pa0_jacobi1"), sol.get(f"{w}_newton_mixed_pa0_jacobi1")
+        if a and b:
+            out["newton_ms"][w] = {"fp64": round(a["ms"], 2), "mixed": round(b["ms"], 2),
+                                   "mixed_speedup_at_equal_residual": round(a["ms"] / b["ms"], 3),
+                                   "res_final_rel": [a["res_final_rel"], b["res_final_rel"]]}
+        a, b = sol.get(f"{w}_adjoint_gradient_fp64_pa0"), sol.get(f"{w}_adjoint_gradient_mixed_pa0")
+        if a and b:
+            out["adjoint_gradient_ms"][w] = {"fp64": round(a["ms"], 2), "mixed": round(b["ms"], 2),
+                                             "mixed_grad_rel_diff": b.get("grad_rel_diff_vs_fp64")}
+    mc = rows.get("mall_cold", {})
+    if "c4" in mc:
+        out["c4_cold_apply"] = {"us": round(mc["c4"]["cold_us"], 2), "hbm_frac": round(mc["c4"]["hbm_frac_cold"], 4),
+                                "hbm_frac_design_bytes": round(mc["c4"]["hbm_frac_cold_design_bytes"], 4),
+                                "copy_GBs": round(mc["copy_GBs"], 1)}
+    if "mixed_error" in rows:
+        out["mixed_vs_fp64_jvp_rel_error"] = rows["mixed_error"]
     return out
 
 
@@ -572,7 +616,7 @@ def main():
                       "order_k": w.k, "nq": w.nq, "p": w.p, "eps": w.eps, "seed": w.seed,
                       "parallelism": "single GPU", "settle_s": args.settle},
            "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")},
-           "roofline_detail": roof, "cpu_baseline": cpu, "rows": rows}
+           "roofline_detail": roof, "cpu_baseline": cpu, "summary": summary(rows), "rows": rows}
     print(json.dumps(out), flush=True)
 
 
