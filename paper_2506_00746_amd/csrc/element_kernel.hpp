@@ -242,84 +242,77 @@ __device__ __forceinline__ double wave_sum(const T* vals, int n, int lane) {
   return s;
 }
 
-// Phase A for NF fields: gather lines (c,b) of the fields through the map and
-// contract in x.  Slot f of the x-pass buffer receives field src[f].  UNIT:
-// the last field is not gathered but is the unit vector of local node
-// unit_j (a tangent direction of the element-level forward mode).  e0 is the
-// global index of the batch's first element.
-template <int D1, int NQ, int EB, int NT, int XSTRIDE, int XQ, int NF, class T, class TB, bool UNIT = false>
-__device__ __forceinline__ void phase_a(const TB& tb, const ElemParams& P, const double* const (&src)[NF],
-                                        T* Xs, int e0, int n_valid, int tid, const int (*sE)[3],
-                                        int unit_j = 0) {
+// G for one phase-A line (c, b) of element e (global index): the D1 DOFs of
+// the x-line (k ex + a, k ey + b, k ez + c) of each of the NG fields, read
+// straight from HBM through the stored map or the same map computed from the
+// lattice; Dirichlet DOFs (on the cube's boundary) read as 0, and so does an
+// element past the end of the mesh (valid false).
+template <int D1, int NG, class T>
+__device__ __forceinline__ void gather_line(const ElemParams& P, const double* const (&src)[NG], int e, bool valid,
+                                            int cb, T (&in)[NG][D1]) {
   constexpr int Ne = D1 * D1 * D1;
-  constexpr int XS = D1 * NQ * XQ;
-  constexpr int NG = UNIT ? NF - 1 : NF;  // gathered fields
-  for (int l = tid; l < EB * D1 * D1; l += NT) {
-    const int el = l / (D1 * D1), cb = l - el * (D1 * D1);
+  if (valid && P.emap != nullptr) {
+    const int32_t* m = P.emap + (int64_t)e * Ne + cb * D1;
+#pragma unroll
+    for (int a = 0; a < D1; ++a) {
+      const int idx = m[a];
+#pragma unroll
+      for (int f = 0; f < NG; ++f) in[f][a] = idx >= 0 ? (T)src[f][idx] : T(0);
+    }
+  } else if (valid) {
+    const uint32_t t = fastdiv((uint32_t)e, P.div_nx), z = fastdiv(t, P.div_ny);
+    const int ex = (int)((uint32_t)e - t * (uint32_t)P.nx), ey = (int)(t - z * (uint32_t)P.ny), ez = (int)z;
     const int c = cb / D1, b = cb - c * D1;
-    T in[NF][D1];
-    if (el < n_valid && P.emap != nullptr) {
-      const int32_t* m = P.emap + (int64_t)(e0 + el) * Ne + cb * D1;
+    const int I0 = P.k * ex, J = P.k * ey + b, K = P.k * ez + c;
+    const bool row = J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
+    const int64_t base = I0 + (int64_t)P.Lx * (J + (int64_t)P.Ly * K);
+    // every node of a valid element lies in the lattice: load unconditionally
+    // (no branch per load) and zero the Dirichlet ones
 #pragma unroll
-      for (int a = 0; a < D1; ++a) {
-        const int idx = m[a];
+    for (int a = 0; a < D1; ++a) {
+      const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
 #pragma unroll
-        for (int f = 0; f < NG; ++f) in[f][a] = idx >= 0 ? (T)src[f][idx] : T(0);
+      for (int f = 0; f < NG; ++f) {
+        const double val = src[f][base + a];
+        in[f][a] = ok ? (T)val : T(0);
       }
-    } else if (el < n_valid) {
-      // the same map computed from the lattice: node (k ex + a, k ey + b, k ez + c),
-      // Dirichlet nodes (on the cube's boundary) read as 0
-      const int I0 = P.k * sE[el][0], J = P.k * sE[el][1] + b, K = P.k * sE[el][2] + c;
-      const bool row = J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
-      const int64_t base = I0 + (int64_t)P.Lx * (J + (int64_t)P.Ly * K);
-      // every node of a valid element lies in the lattice: load unconditionally
-      // (no branch per load) and zero the Dirichlet ones
-#pragma unroll
-      for (int a = 0; a < D1; ++a) {
-        const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
-#pragma unroll
-        for (int f = 0; f < NG; ++f) {
-          const double val = src[f][base + a];
-          in[f][a] = ok ? (T)val : T(0);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int f = 0; f < NG; ++f)
-#pragma unroll
-        for (int a = 0; a < D1; ++a) in[f][a] = 0;
     }
-    if constexpr (UNIT) {
+  } else {
 #pragma unroll
-      for (int a = 0; a < D1; ++a) in[NF - 1][a] = cb * D1 + a == unit_j ? T(1) : T(0);
+    for (int f = 0; f < NG; ++f)
+#pragma unroll
+      for (int a = 0; a < D1; ++a) in[f][a] = 0;
+  }
+}
+
+// Phase A's contraction in x of one line: values (B) and x-derivatives (Dx)
+// at the NQ points, into the x-pass buffer at x (the line's slot, [s][qx]
+// with stride XQ, s = 0 values, s = 1 derivatives).
+template <int D1, int NQ, int XQ, class T, class TB>
+__device__ __forceinline__ void xpass_line(const TB& tb, const T (&in)[D1], T* x) {
+  constexpr int XS = D1 * NQ * XQ;
+  if constexpr (Unroll<D1>::full) {
+    // even-odd form
+    T e[EO<D1, NQ>::AP], o[EO<D1, NQ>::AH], y0[NQ], y1[NQ];
+    eo_split<D1, NQ>(in, e, o);
+    eo_forward<D1, NQ, true>(tb.Pb, tb.Nb, e, o, y0);
+    eo_forward<D1, NQ, false>(tb.Px, tb.Nx, e, o, y1);
+#pragma unroll
+    for (int qx = 0; qx < NQ; ++qx) {
+      x[qx * XQ] = y0[qx];
+      x[XS + qx * XQ] = y1[qx];
     }
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      T* x = Xs + el * XSTRIDE + f * 2 * XS + c * NQ * XQ + b;
-      if constexpr (Unroll<D1>::full) {
-        // values (B) and x-derivatives (Dx) at the NQ points, even-odd form
-        T e[EO<D1, NQ>::AP], o[EO<D1, NQ>::AH], y0[NQ], y1[NQ];
-        eo_split<D1, NQ>(in[f], e, o);
-        eo_forward<D1, NQ, true>(tb.Pb, tb.Nb, e, o, y0);
-        eo_forward<D1, NQ, false>(tb.Px, tb.Nx, e, o, y1);
-#pragma unroll
-        for (int qx = 0; qx < NQ; ++qx) {
-          x[qx * XQ] = y0[qx];
-          x[XS + qx * XQ] = y1[qx];
-        }
-      } else {  // high order: full tables, runtime loop (bounded register use)
+  } else {  // high order: full tables, runtime loop (bounded register use)
 #pragma unroll(Unroll<NQ>::full ? NQ : Config<D1, NQ, T>::RUQ)
-        for (int qx = 0; qx < NQ; ++qx) {
-          T s0 = tb.B[qx * D1] * in[f][0], s1 = tb.Dx[qx * D1] * in[f][0];
+    for (int qx = 0; qx < NQ; ++qx) {
+      T s0 = tb.B[qx * D1] * in[0], s1 = tb.Dx[qx * D1] * in[0];
 #pragma unroll
-          for (int a = 1; a < D1; ++a) {
-            s0 += tb.B[qx * D1 + a] * in[f][a];
-            s1 += tb.Dx[qx * D1 + a] * in[f][a];
-          }
-          x[qx * XQ] = s0;
-          x[XS + qx * XQ] = s1;
-        }
+      for (int a = 1; a < D1; ++a) {
+        s0 += tb.B[qx * D1 + a] * in[a];
+        s1 += tb.Dx[qx * D1 + a] * in[a];
       }
+      x[qx * XQ] = s0;
+      x[XS + qx * XQ] = s1;
     }
   }
 }
@@ -460,13 +453,25 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   const int e0 = xcd_remap(blockIdx.x, gridDim.x) * EB;  // batch start, relative to eoff
   const int eoff = ELM ? P.e_first : 0;                   // global index of element 0
   const int n_valid = min(EB, P.E - e0);
-  __shared__ int sE[EB][3];  // (ex, ey, ez) of each element of the batch
-  if (tid < EB) {
-    const uint32_t e = (uint32_t)(eoff + e0 + tid), t = fastdiv(e, P.div_nx), z = fastdiv(t, P.div_ny);
-    sE[tid][0] = (int)(e - t * (uint32_t)P.nx);
-    sE[tid][1] = (int)(t - z * (uint32_t)P.ny);
-    sE[tid][2] = (int)z;
+
+  // ---- global loads first: G (this thread's phase-A line of the gathered
+  // fields) and the batch's coefficients, so that their HBM latency overlaps
+  // the set-up below instead of stalling the phases that use them
+  constexpr int NG = (F == 2 && !PA && !ELM) ? 2 : 1;  // fields gathered from L-vectors
+  static_assert(EB * D1 * D1 <= NT, "phase A takes one line per thread");
+  const bool aline = tid < EB * D1 * D1;
+  const int ael = aline ? tid / (D1 * D1) : 0, acb = aline ? tid - ael * (D1 * D1) : 0;
+  T gin[NG][D1];
+  {
+    const double* const src1[1] = {PA ? P.v : P.u};
+    const double* const src2[2] = {P.u, P.v};
+    if constexpr (NG == 2)
+      gather_line<D1, 2, T>(P, src2, eoff + e0 + ael, aline && ael < n_valid, acb, gin);
+    else
+      gather_line<D1, 1, T>(P, src1, eoff + e0 + ael, aline && ael < n_valid, acb, gin);
   }
+  __shared__ T sRho[EB];  // coefficients of the batch's elements
+  if (tid < EB) sRho[tid] = (P.rho != nullptr && tid < n_valid) ? (T)P.rho[eoff + e0 + tid] : T(1);
 
   for (int i = tid; i < NQ * D1; i += NT) {
     const int q = i / D1, a = i - q * D1;
@@ -491,22 +496,20 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
     }
   }
 
-  __syncthreads();  // sE, tables and vertices visible to every thread
+  __syncthreads();  // tables, coefficients and vertices visible to every thread
 
-  // ---- A: gather + x-pass ---------------------------------------------------
-  if constexpr (PA) {
-    const double* const src[1] = {P.v};
-    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
-  } else if constexpr (ELM) {
-    const double* const src[2] = {P.u, P.u};  // the second field is the unit direction
-    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 2, T, Tab<D1, NQ, T>, true>(tb, P, src, Xs, eoff + e0, n_valid, tid, sE,
-                                                                       (int)blockIdx.y);
-  } else if constexpr (F == 2 && !SEQ) {
-    const double* const src[2] = {P.u, P.v};
-    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 2, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
-  } else {
-    const double* const src[1] = {P.u};
-    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+  // ---- A: x-pass of the gathered lines --------------------------------------
+  if (aline) {
+    T* x = Xs + ael * L::XSTR + (acb / D1) * NQ * L::XQ + (acb % D1);
+    xpass_line<D1, NQ, L::XQ, T>(tb, gin[0], x);
+    if constexpr (ELM) {  // the second field is the unit direction of local node blockIdx.y
+      T unit[D1];
+#pragma unroll
+      for (int a = 0; a < D1; ++a) unit[a] = acb * D1 + a == (int)blockIdx.y ? T(1) : T(0);
+      xpass_line<D1, NQ, L::XQ, T>(tb, unit, x + 2 * L::XS);
+    } else if constexpr (NG == 2 && !SEQ) {
+      xpass_line<D1, NQ, L::XQ, T>(tb, gin[1], x + 2 * L::XS);
+    }
   }
   __syncthreads();
 
@@ -528,8 +531,9 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       column_forward<D1, NQ, L::XQ, T>(tb, Xs + el * L::XSTR, By, Dy, qx, g[0]);
     }
     __syncthreads();
-    const double* const src[1] = {P.v};
-    phase_a<D1, NQ, EB, NT, L::XSTR, L::XQ, 1, T>(tb, P, src, Xs, e0, n_valid, tid, sE);
+    if constexpr (NG == 2) {
+      if (aline) xpass_line<D1, NQ, L::XQ, T>(tb, gin[1], Xs + ael * L::XSTR + (acb / D1) * NQ * L::XQ + (acb % D1));
+    }
     __syncthreads();
   }
   const int l = tid;  // one column per thread
@@ -569,8 +573,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
   }
   if (L::ALIAS) __syncthreads();  // x-pass buffer consumed: the z-back may overwrite it
   if (active && !QSTORE) {
-    const bool valid = el < n_valid;
-    const T rho = (P.rho != nullptr && valid) ? (T)P.rho[eoff + e0 + el] : T(1);
+    const T rho = sRho[el];
     const T wxy = sW[qx] * sW[qy];
     // geometry: affine -> constant diagonal; curved -> Jg = J0 + xi_z J1 (column 2 constant)
     T J0[3][3], J1[3][2];
