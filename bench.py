@@ -514,6 +514,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="c3")
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "mixed"],
+                    help="precision of the timed Jacobian apply (the headline is FP64; mixed is for profiling runs)")
     ap.add_argument("--settle", type=float, default=0.5,
                     help="seconds of untimed applies before the warm-up steps (GPU clocks reach steady state)")
     ap.add_argument("--repeats", type=int, default=5,
@@ -553,28 +555,31 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    def jvp64():
-        prob.jacobian_apply(u, v, out=jv)
+    prec = args.prec
+    kname = "element_jvp_f64" if prec == "fp64" else "element_jvp_f32"
 
-    log(f"[bench] {w.name}: N={N} E={w.n_elems} timed JVP fp64 x{args.steps}")
+    def jvp64():
+        prob.jacobian_apply(u, v, out=jv, prec=prec)
+
+    log(f"[bench] {w.name}: N={N} E={w.n_elems} timed JVP {prec} x{args.steps}")
     settle(jvp64, args.settle)
     ms = timed_loop(jvp64, args.steps, args.warmup)
     value = N / (ms * 1e-3) / 1e9
     stats = kernel_profile(prob, jvp64, min(args.steps, 50))
-    k_ms = element_kernel_ms(prob, u, v, "jvp", "fp64", args.steps, args.warmup)
-    roof = roofline(prob, "jvp", "fp64", stats, "element_jvp_f64", kernel_ms=k_ms)
-    roof["traffic"] = stored_traffic(w.name, "element_jvp_f64")
+    k_ms = element_kernel_ms(prob, u, v, "jvp", prec, args.steps, args.warmup)
+    roof = roofline(prob, "jvp", prec, stats, kname, kernel_ms=k_ms)
+    roof["traffic"] = stored_traffic(w.name, kname)
     reps = sorted(timed_loop(jvp64, args.steps, 0) for _ in range(args.repeats))
     rep_med = reps[len(reps) // 2] if reps else ms
-    log(f"[bench] JVP fp64 {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s (median of {len(reps)} more windows "
+    log(f"[bench] JVP {prec} {ms * 1e3:.1f} us/apply = {value:.2f} GDOF/s (median of {len(reps)} more windows "
         f"{rep_med * 1e3:.1f} us); element kernel {k_ms * 1e3:.2f} us back-to-back; per-launch events {stats}")
 
-    rows = {w.name: {"jvp_fp64": {"GDOF/s": value, "us_per_apply": ms * 1e3, "kernel_us": roof["avg_us"],
+    rows = {w.name: {f"jvp_{prec}": {"GDOF/s": value, "us_per_apply": ms * 1e3, "kernel_us": roof["avg_us"],
                                   "kernel_bound": roof["bound"], "kernel_frac": roof["frac"],
                                   "repeat_windows_us": [t * 1e3 for t in reps],
                                   "repeat_median_GDOF/s": N / (rep_med * 1e-3) / 1e9,
                                   "gather_t_us": stats.get("gather_transpose", {"avg_ms": 0.0})["avg_ms"] * 1e3}}}
-    if not args.no_extras:
+    if not args.no_extras and prec == "fp64":
         rows[w.name].update(apply_rows(prob, u, v, w, args,
                                        only=("jvp_mixed", "residual_fp64", "residual_jvp_fp64")))
         rows[w.name]["jvp_mixed"]["speedup_vs_fp64_apply"] = rows[w.name]["jvp_mixed"]["GDOF/s"] / value
@@ -611,7 +616,8 @@ def main():
 
     out = {"metric": METRIC, "value": value, "unit": "GDOF/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "vs_baseline": None, "dtype": "f64" if prec == "fp64" else "f32 element stage, f64 G^T",
+           "data": "synthetic",
            "config": {"workload": f"{w.name}: {w.note}", "n_dofs": N, "n_elems": w.n_elems,
                       "order_k": w.k, "nq": w.nq, "p": w.p, "eps": w.eps, "seed": w.seed,
                       "parallelism": "single GPU", "settle_s": args.settle},
