@@ -26,6 +26,7 @@ SMALL = [
     Workload("q1-curved", 5, 4, 3, 1, 2, 2.5, 1e-2, 27, perturb=True, rho=True),
     Workload("q2-nq4-generic-p", 3, 3, 4, 2, 4, 1.5, 0.1, 28, perturb=True),
     Workload("q2-p2", 4, 3, 2, 2, 3, 2.0, 1e-2, 29),
+    Workload("q7-affine-rho-generic-p", 3, 3, 1, 7, 9, 1.7, 0.1, 30, rho=True),  # ragged last Q7 batch
 ]
 IDS = [w.name for w in SMALL]
 
