@@ -65,42 +65,62 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
 // lattice lies in element ex = I/k (local a = I%k) and, when I is a multiple
 // of k, also in ex-1 (local a = k); likewise in y and z.  The contributions are
 // summed in ascending element order, which is the order of the explicit map.
-// Dirichlet DOFs (on the lattice boundary) get exactly 0.
-template <class TE, bool TWO>
-__device__ __forceinline__ void lattice_row_sum(const LatticeDims& d, const TE* __restrict__ Y0,
-                                                const TE* __restrict__ Y1, int64_t i, double& s0, double& s1) {
-  // n < 2^31 (checked at set-up): 32-bit unsigned index arithmetic
-  const uint32_t iu = (uint32_t)i, t = fastdiv(iu, d.div_Lx);
-  const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)fastdiv(t, d.div_Ly), J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
-  s0 = 0;
-  s1 = 0;
-  if (I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1) {
+// Dirichlet DOFs (on the lattice boundary) and indices past n get exactly 0.
+//
+// The gather is bound by memory latency (each wavefront's loads touch one
+// short run per element), so a thread takes U DOFs and issues the candidate
+// loads of all of them before it adds any.
+template <class TE, bool TWO, int U>
+__device__ __forceinline__ void lattice_rows_sum(const LatticeDims& d, const TE* __restrict__ Y0,
+                                                 const TE* __restrict__ Y1, const int64_t (&i)[U], int64_t n,
+                                                 double (&s0)[U], double (&s1)[U]) {
+  TE v0[U][8], v1[U][8];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    // n < 2^31 (checked at set-up): 32-bit unsigned index arithmetic
+    const bool in = i[u] < n;
+    const uint32_t iu = in ? (uint32_t)i[u] : 0u, t = fastdiv(iu, d.div_Lx);
+    const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)fastdiv(t, d.div_Ly),
+              J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
+    const bool inner = in && I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1;
     const int k = d.k, D1 = k + 1;
     // up to two candidate elements per direction: lower (index/k - 1, local k)
     // when the index is a multiple of k, and upper (index/k, local index%k)
     const int ix = (int)fastdiv((uint32_t)I, d.div_k), iy = (int)fastdiv((uint32_t)J, d.div_k),
               iz = (int)fastdiv((uint32_t)K, d.div_k);
     const bool lx = I - k * ix == 0, ly = J - k * iy == 0, lz = K - k * iz == 0;
-    TE v0[8], v1[8];
 #pragma unroll
     for (int q = 0; q < 8; ++q) {  // q = tx + 2 ty + 4 tz, ascending element order
       const int tx = q & 1, ty = (q >> 1) & 1, tz = q >> 2;
-      const bool use = (tx || lx) && (ty || ly) && (tz || lz);
+      const bool use = inner && (tx || lx) && (ty || ly) && (tz || lz);
       const int ex = ix - 1 + tx, ey = iy - 1 + ty, ez = iz - 1 + tz;
       const int a = I - k * ex, b = J - k * ey, c = K - k * ez;
       const uint32_t j = ((uint32_t)ex + (uint32_t)d.nx * (ey + (uint32_t)d.ny * ez)) * (uint32_t)(D1 * D1 * D1) +
                          a + D1 * (b + D1 * c);
-      v0[q] = use ? Y0[j] : TE(0);
-      if (TWO) v1[q] = use ? Y1[j] : TE(0);
+      v0[u][q] = use ? Y0[j] : TE(0);
+      if (TWO) v1[u][q] = use ? Y1[j] : TE(0);
     }
-    // adding +0 for absent candidates leaves the ordered sum bitwise unchanged
+  }
+  // Adding +0 for absent candidates leaves the ordered sum unchanged.  The
+  // sum starts from the first candidate rather than from 0 (the same value:
+  // x + 0 = x, and -0 only differs from 0 in sign), so that no addition can
+  // be moved next to a load and make the thread wait for it there.
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      s0 += (double)v0[q];
-      if (TWO) s1 += (double)v1[q];
+  for (int u = 0; u < U; ++u) {
+    s0[u] = (double)v0[u][0];
+    s1[u] = TWO ? (double)v1[u][0] : 0.0;
+#pragma unroll
+    for (int q = 1; q < 8; ++q) {
+      s0[u] += (double)v0[u][q];
+      if (TWO) s1[u] += (double)v1[u][q];
     }
   }
 }
+
+// DOFs per thread of the plain lattice gather.  Two measured best: at 64^3
+// Q4 the FP64 gather takes 120 us against 124 with one DOF per thread (FP32
+// E-vector 115 against 127); four gain nothing.
+constexpr int kGatherUnroll = 2;
 
 template <class TE, bool TWO>
 __global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDims d, const TE* __restrict__ Y0,
@@ -108,18 +128,28 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDi
                                                                        const double* __restrict__ bm,
                                                                        double* __restrict__ out0,
                                                                        double* __restrict__ out1, int64_t n) {
-  const int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kVecThreads + threadIdx.x;
-  if (i >= n) return;
-  double s0, s1;
-  lattice_row_sum<TE, TWO>(d, Y0, Y1, i, s0, s1);
-  if (bm != nullptr) s0 -= bm[i];  // bm is 0 on Dirichlet DOFs
-  out0[i] = s0;
-  if (TWO) out1[i] = s1;
+  constexpr int U = kGatherUnroll;
+  const int64_t i0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * (kVecThreads * U) + threadIdx.x;
+  int64_t i[U];
+  double bv[U], s0[U], s1[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    i[u] = i0 + u * kVecThreads;
+    bv[u] = (bm != nullptr && i[u] < n) ? bm[i[u]] : 0.0;
+  }
+  lattice_rows_sum<TE, TWO, U>(d, Y0, Y1, i, n, s0, s1);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    if (i[u] >= n) continue;
+    if (bm != nullptr) s0[u] -= bv[u];  // bm is 0 on Dirichlet DOFs
+    out0[i[u]] = s0[u];
+    if (TWO) out1[i[u]] = s1[u];
+  }
 }
 
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
                                    const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
-  const int nb = vec_blocks(n);
+  const int nb = vec_blocks((n + kGatherUnroll - 1) / kGatherUnroll);
   if (fp32) {
     if (Y1)
       hipLaunchKernelGGL((gather_t_lattice_kernel<float, true>), dim3(nb), dim3(kVecThreads), 0, s, d,
@@ -287,23 +317,39 @@ __device__ __forceinline__ double gather_block_sum(double v) {
 // the end are clamped to n-1 for the loads and skipped for stores and sums.
 // Each thread still adds its DOFs in ascending order.
 
-// q = G^T Y and partial[b] = sum of p[i] q[i] over block b's share: one DOF
-// per thread (grid-stride only past kGatherDotMaxBlocks blocks), as in the
-// plain gather, so that the whole grid's loads are in flight at once.
+// q = G^T Y and partial[b] = sum of p[i] q[i] over block b's share: a thread
+// takes the DOFs i, i + S, i + 2S, ... (S = the grid's thread count) in that
+// order, kGatherDotUnroll of them per pass with all their loads issued first.
+// One per pass measured fastest: the grid already covers 4M DOFs per pass
+// (at 64^3 Q4 the gather takes 143 us with one, 142-148 with two, 155 with
+// four, whose registers cost occupancy).
+constexpr int kGatherDotUnroll = 1;
+
 template <class TE>
 __global__ __launch_bounds__(kGatherDotThreads) void gather_t_lattice_dot_kernel(LatticeDims d,
                                                                                  const TE* __restrict__ Y,
                                                                                  const double* __restrict__ p,
                                                                                  double* __restrict__ q, int64_t n,
                                                                                  double* __restrict__ partial) {
+  constexpr int U = kGatherDotUnroll;
   double acc = 0;
   const int64_t stride = (int64_t)gridDim.x * kGatherDotThreads;
-  for (int64_t i = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kGatherDotThreads + threadIdx.x; i < n;
-       i += stride) {
-    double s0, s1;
-    lattice_row_sum<TE, false>(d, Y, nullptr, i, s0, s1);
-    q[i] = s0;
-    acc += p[i] * s0;
+  for (int64_t i0 = (int64_t)xcd_remap(blockIdx.x, gridDim.x) * kGatherDotThreads + threadIdx.x; i0 < n;
+       i0 += U * stride) {
+    int64_t i[U];
+    double pv[U], s0[U], s1[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      i[u] = i0 + u * stride;
+      pv[u] = i[u] < n ? p[i[u]] : 0.0;
+    }
+    lattice_rows_sum<TE, false, U>(d, Y, nullptr, i, n, s0, s1);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (i[u] >= n) break;
+      q[i[u]] = s0[u];
+      acc += pv[u] * s0[u];
+    }
   }
   acc = gather_block_sum(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
