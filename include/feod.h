@@ -126,9 +126,11 @@ typedef struct {
  * max_cg 20000, max_ls 30, check_every 10, FP64, init_poisson 1, jacobi 1,
  * partial_assembly 0.  Jacobi preconditioning halves the CG iterations and
  * the Newton time on the 48^3 Q2 and 32^3 Q3 workloads.  Partial assembly
- * measured within 1.5% of the fused Jacobian action over whole Newton solves
- * on both (31.03 vs 30.99 ms and 39.00 vs 38.58 ms), so the default keeps the
- * fused action, whose quadrature data never leaves the registers. */
+ * measured within 2.5% of the fused Jacobian action over whole Newton solves
+ * on both (29.8 vs 30.5 ms and 38.8 vs 38.2 ms), so the default keeps the
+ * fused action, whose quadrature data never leaves the registers.  At Q7 it
+ * pays: the curved 16^3 Q7 Newton solve takes 100.0 instead of 110.7 ms and
+ * its adjoint gradient 58.0 instead of 64.1 ms (FP64), so set it for Q6+. */
 void feod_default_opts(feod_solver_opts* opts);
 
 /* Build the mesh, element-to-DOF map G, transposed map for G^T, 1D tables and

@@ -102,9 +102,11 @@ __device__ __forceinline__ void lattice_rows_sum(const LatticeDims& d, const TE*
     }
   }
   // Adding +0 for absent candidates leaves the ordered sum unchanged.  The
-  // sum starts from the first candidate rather than from 0 (the same value:
-  // x + 0 = x, and -0 only differs from 0 in sign), so that no addition can
-  // be moved next to a load and make the thread wait for it there.
+  // sum starts from the first candidate rather than from 0, so that no
+  // addition can be moved next to a load and make the thread wait for it
+  // there; the final + 0 turns a -0 into +0, which makes the result bitwise
+  // that of 0 + c_1 + c_2 + ... (the explicit map's sum): the two running
+  // sums can differ only in the sign of a zero.
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     s0[u] = (double)v0[u][0];
@@ -114,6 +116,8 @@ __device__ __forceinline__ void lattice_rows_sum(const LatticeDims& d, const TE*
       s0[u] += (double)v0[u][q];
       if (TWO) s1[u] += (double)v1[u][q];
     }
+    s0[u] += 0.0;
+    if (TWO) s1[u] += 0.0;
   }
 }
 
