@@ -265,13 +265,7 @@ feod_status run_element(feod_ctx* c, int op, int prec, const ElemParams& P) {
   return timed(c, op_name(op, prec), [&] { return fn(P, c->stream); });
 }
 
-LatticeDims lattice_dims(const feod_ctx* c) {
-  LatticeDims d{c->nx, c->ny, c->nz, c->k, (int32_t)c->lat.Lx, (int32_t)c->lat.Ly, (int32_t)c->lat.Lz, {}, {}, {}};
-  d.div_Lx = make_fastdiv((uint32_t)d.Lx);
-  d.div_Ly = make_fastdiv((uint32_t)d.Ly);
-  d.div_k = make_fastdiv((uint32_t)d.k);
-  return d;
-}
+LatticeDims lattice_dims(const feod_ctx* c) { return make_lattice_dims(c->nx, c->ny, c->nz, c->k); }
 
 // G^T of one or two E-vectors: y0 = G^T Y0 - bm (bm may be null), y1 = G^T Y1
 hipError_t gather_t(feod_ctx* c, const void* Y0, const void* Y1, bool fp32, const double* bm, double* y0,

@@ -101,7 +101,12 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
 struct LatticeDims {
   int32_t nx, ny, nz, k, Lx, Ly, Lz;
   FastDiv div_Lx, div_Ly, div_k;  // DOF index -> (I, J, K) -> element index
+  // E-vector entries per element, (k+1)^3, and how far the lower candidate
+  // element's entry of a DOF sits before the upper one's, per direction:
+  // Ne - k, nx Ne - k (k+1), nx ny Ne - k (k+1)^2
+  uint32_t ne, dlx, dly, dlz;
 };
+LatticeDims make_lattice_dims(int32_t nx, int32_t ny, int32_t nz, int32_t k);
 // Same sums as launch_gather_t, in the same (ascending E-vector position)
 // order, with each DOF's element list computed from the lattice.
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,

@@ -61,6 +61,26 @@ hipError_t launch_gather_t(const int32_t* off, const int32_t* idx, const void* Y
   return hipGetLastError();
 }
 
+LatticeDims make_lattice_dims(int32_t nx, int32_t ny, int32_t nz, int32_t k) {
+  LatticeDims d{};
+  d.nx = nx;
+  d.ny = ny;
+  d.nz = nz;
+  d.k = k;
+  d.Lx = k * nx + 1;
+  d.Ly = k * ny + 1;
+  d.Lz = k * nz + 1;
+  d.div_Lx = make_fastdiv((uint32_t)d.Lx);
+  d.div_Ly = make_fastdiv((uint32_t)d.Ly);
+  d.div_k = make_fastdiv((uint32_t)k);
+  const uint32_t D1 = (uint32_t)k + 1, ne = D1 * D1 * D1;
+  d.ne = ne;
+  d.dlx = ne - (uint32_t)k;
+  d.dly = (uint32_t)nx * ne - (uint32_t)k * D1;
+  d.dlz = (uint32_t)nx * (uint32_t)ny * ne - (uint32_t)k * D1 * D1;
+  return d;
+}
+
 // Computed transposed map: DOF (I,J,K) of the (k nx+1)(k ny+1)(k nz+1) node
 // lattice lies in element ex = I/k (local a = I%k) and, when I is a multiple
 // of k, also in ex-1 (local a = k); likewise in y and z.  The contributions are
@@ -83,20 +103,21 @@ __device__ __forceinline__ void lattice_rows_sum(const LatticeDims& d, const TE*
     const int I = (int)(iu - t * (uint32_t)d.Lx), K = (int)fastdiv(t, d.div_Ly),
               J = (int)(t - (uint32_t)K * (uint32_t)d.Ly);
     const bool inner = in && I > 0 && I < d.Lx - 1 && J > 0 && J < d.Ly - 1 && K > 0 && K < d.Lz - 1;
-    const int k = d.k, D1 = k + 1;
-    // up to two candidate elements per direction: lower (index/k - 1, local k)
-    // when the index is a multiple of k, and upper (index/k, local index%k)
-    const int ix = (int)fastdiv((uint32_t)I, d.div_k), iy = (int)fastdiv((uint32_t)J, d.div_k),
-              iz = (int)fastdiv((uint32_t)K, d.div_k);
-    const bool lx = I - k * ix == 0, ly = J - k * iy == 0, lz = K - k * iz == 0;
+    // The upper candidate (index/k, local index%k) always exists for an
+    // interior DOF; the lower one in a direction (index/k - 1, local k)
+    // exists when the index is a multiple of k, and its E-vector position is
+    // the upper one's minus a constant of that direction.
+    const uint32_t k = (uint32_t)d.k, D1 = k + 1;
+    const uint32_t ix = fastdiv((uint32_t)I, d.div_k), iy = fastdiv((uint32_t)J, d.div_k),
+                   iz = fastdiv((uint32_t)K, d.div_k);
+    const uint32_t ai = (uint32_t)I - k * ix, bi = (uint32_t)J - k * iy, ci = (uint32_t)K - k * iz;
+    const bool lx = ai == 0, ly = bi == 0, lz = ci == 0;
+    const uint32_t j7 = (ix + (uint32_t)d.nx * (iy + (uint32_t)d.ny * iz)) * d.ne + ai + D1 * (bi + D1 * ci);
 #pragma unroll
     for (int q = 0; q < 8; ++q) {  // q = tx + 2 ty + 4 tz, ascending element order
       const int tx = q & 1, ty = (q >> 1) & 1, tz = q >> 2;
       const bool use = inner && (tx || lx) && (ty || ly) && (tz || lz);
-      const int ex = ix - 1 + tx, ey = iy - 1 + ty, ez = iz - 1 + tz;
-      const int a = I - k * ex, b = J - k * ey, c = K - k * ez;
-      const uint32_t j = ((uint32_t)ex + (uint32_t)d.nx * (ey + (uint32_t)d.ny * ez)) * (uint32_t)(D1 * D1 * D1) +
-                         a + D1 * (b + D1 * c);
+      const uint32_t j = j7 - (tx ? 0u : d.dlx) - (ty ? 0u : d.dly) - (tz ? 0u : d.dlz);
       v0[u][q] = use ? Y0[j] : TE(0);
       if (TWO) v1[u][q] = use ? Y1[j] : TE(0);
     }
