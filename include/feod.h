@@ -136,7 +136,9 @@ void feod_default_opts(feod_solver_opts* opts);
 /* Build the mesh, element-to-DOF map G, transposed map for G^T, 1D tables and
  * load vector on the host (no GPU call).  *out receives a new context.
  * Returns FEOD_EINVAL for bad sizes/parameters or an inverted element, and
- * FEOD_EUNSUPPORTED for a (k, nq) pair without a compiled kernel. */
+ * FEOD_EUNSUPPORTED for a (k, nq) pair without a compiled kernel or a mesh
+ * whose DOF count or E-vector length (elements x (k+1)^3) reaches 2^31 - 1
+ * (the kernels' 32-bit indices); nothing is allocated in that case. */
 feod_status feod_setup_mesh(const feod_mesh_desc* desc, feod_ctx** out);
 
 /* Bytes of device workspace the context needs (maps, tables, load, rho,

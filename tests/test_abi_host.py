@@ -76,6 +76,12 @@ def test_setup_rejects_bad_input():
     assert setup(eps=0.0, p=1.5)[0] == feod.feod.FEOD_EINVAL
     st, msg = setup(order_k=6, nq=2)
     assert st == feod.feod.FEOD_EUNSUPPORTED and "k=6" in msg
+    # the largest meshes the 32-bit DOF and E-vector indices take, checked
+    # before anything is allocated: N = 1601^3 > 2^31, then E Ne = 162^3 512 > 2^31
+    # with N = 1135^3 < 2^31
+    for big in (dict(nx=400, ny=400, nz=400, order_k=4, nq=6), dict(nx=162, ny=162, nz=162, order_k=7, nq=9)):
+        st, msg = setup(**big)
+        assert st == feod.feod.FEOD_EUNSUPPORTED and "too large" in msg, (big, msg)
     # inverted element
     w = Workload("t", 2, 2, 2, 2, 3, 3.0, 1e-2, 5, perturb=True)
     v = make_inputs(w)["vertices"].copy()
