@@ -346,11 +346,8 @@ struct CgResult {
 // G^T of the E-vector Y0 into q, with the partial sums of p.q (CG slot C_PQ)
 feod_status gather_t_dot(feod_ctx* c, bool fp32, const double* p, double* q) {
   return timed(c, "gather_transpose_dot", [&] {
-    if (c->explicit_maps)
-      return launch_gather_t_dot(nullptr, c->d_toff, c->d_tidx, c->d_Y0, fp32, p, q, c->lat.N,
-                                 c->cg_part(C_PQ), c->stream);
-    LatticeDims d = lattice_dims(c);
-    return launch_gather_t_dot(&d, nullptr, nullptr, c->d_Y0, fp32, p, q, c->lat.N, c->cg_part(C_PQ), c->stream);
+    return launch_gather_t_dot(lattice_dims(c), c->explicit_maps, c->d_toff, c->d_tidx, c->d_Y0, fp32, p, q,
+                               c->lat.N, c->cg_part(C_PQ), c->stream);
   });
 }
 

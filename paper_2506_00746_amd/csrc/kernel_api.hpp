@@ -124,17 +124,20 @@ hipError_t launch_reduce_final(const double* partial, int nparts, double* out, d
 constexpr int kCgBlocks = 512;   // partial sums per CG inner product (two blocks per CU)
 constexpr int kCgThreads = 512;  // threads per CG vector block
 constexpr int kCgUnroll = 4;     // DOFs per thread per grid-stride pass
-// q = G^T Y (lattice map when d != null, else the CSR map off/idx) and
+// q = G^T Y (the lattice map, or with csr the CSR map off/idx) and
 // partial[b] = block b's share of p.q, for gather_dot_blocks(n) blocks of
-// kGatherDotThreads (one DOF per thread up to kGatherDotMaxBlocks blocks).
+// kGatherDotThreads (one DOF per thread up to kGatherDotMaxBlocks blocks);
+// both maps take the DOFs in the same order, so their partials are bitwise
+// equal.
 constexpr int kGatherDotThreads = 1024;
 constexpr int kGatherDotMaxBlocks = 4096;
 inline int gather_dot_blocks(int64_t n) {
   const int64_t b = (n + kGatherDotThreads - 1) / kGatherDotThreads;
   return (int)(b < 1 ? 1 : (b > kGatherDotMaxBlocks ? kGatherDotMaxBlocks : b));
 }
-hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
-                               bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s);
+hipError_t launch_gather_t_dot(const LatticeDims& dims, bool csr, const int32_t* off, const int32_t* idx,
+                               const void* Y, bool fp32, const double* p, double* q, int64_t n, double* partial,
+                               hipStream_t s);
 // x = 0, r = b, z = dinv r (z may alias r when dinv is null), p = z, partials of r.z and r.r
 hipError_t launch_cg_init(double* x, double* r, double* z, double* p, const double* b, const double* dinv,
                           int64_t n, double* part_rz, double* part_rr, hipStream_t s);

@@ -177,10 +177,41 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDi
 // A wavefront's loads then read th adjacent x-lines of each element it
 // touches (contiguous in the E-vector) instead of one line of 64 DOFs, which
 // spans 64/k elements: at Q4, 4 spans of 160 bytes instead of 16 of 40.
+
 struct GatherTiles {
   uint32_t th, tw, ntx, nty, ntiles;  // tile shape, tiles per row span and per plane, total
   FastDiv div_tw, div_ntx, div_nplane;
 };
+
+GatherTiles make_gather_tiles(const LatticeDims& d) {
+  GatherTiles g{};
+  g.th = (uint32_t)d.k;
+  g.tw = 64 / g.th;
+  g.ntx = ((uint32_t)d.Lx + g.tw - 1) / g.tw;
+  g.nty = ((uint32_t)d.Ly + g.th - 1) / g.th;
+  g.ntiles = g.ntx * g.nty * (uint32_t)d.Lz;
+  g.div_tw = make_fastdiv(g.tw);
+  g.div_ntx = make_fastdiv(g.ntx);
+  g.div_nplane = make_fastdiv(g.ntx * g.nty);
+  return g;
+}
+
+// Tiles where they measured faster: an FP64 E-vector with k = 2 or 4 (whole
+// 64-lane tiles).  At 64^3 Q4 the plain gather takes 98.5 us against 117.5
+// in lattice order, at 48^3 Q2 10.5 against 11.2; with k = 3 or 7 (63-lane
+// tiles) and for FP32 E-vectors lattice order is 5-27% faster.
+inline bool use_tiles(const LatticeDims& d, bool fp32) { return !fp32 && (d.k == 2 || d.k == 4); }
+
+// DOF of the lane at (dx, dy) of tile t, or n when that lane falls outside
+// the lattice (or t is past the last tile).
+__device__ __forceinline__ int64_t tile_dof(const LatticeDims& d, const GatherTiles& g, uint32_t t, uint32_t dx,
+                                            uint32_t dy, int64_t n) {
+  const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * (g.ntx * g.nty);
+  const uint32_t jt = fastdiv(rem, g.div_ntx), it = rem - jt * g.ntx;
+  const uint32_t I = it * g.tw + dx, J = jt * g.th + dy;
+  const bool ok = t < g.ntiles && dy < g.th && I < (uint32_t)d.Lx && J < (uint32_t)d.Ly;
+  return ok ? (int64_t)I + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz) : n;
+}
 
 template <class TE, bool TWO>
 __global__ __launch_bounds__(kVecThreads) void gather_t_tiles_kernel(LatticeDims d, GatherTiles g,
@@ -197,12 +228,7 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_tiles_kernel(LatticeDims
   double bv[U], s0[U], s1[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
-    const uint32_t t = w0 * U + u;  // this wavefront's u-th tile
-    const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * (g.ntx * g.nty);
-    const uint32_t jt = fastdiv(rem, g.div_ntx), it = rem - jt * g.ntx;
-    const uint32_t I = it * g.tw + dx, J = jt * g.th + dy;
-    const bool ok = t < g.ntiles && dy < g.th && I < (uint32_t)d.Lx && J < (uint32_t)d.Ly;
-    i[u] = ok ? (int64_t)I + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz) : n;
+    i[u] = tile_dof(d, g, w0 * U + u, dx, dy, n);  // this wavefront's u-th tile
     bv[u] = (bm != nullptr && i[u] < n) ? bm[i[u]] : 0.0;
   }
   lattice_rows_sum<TE, TWO, U>(d, Y0, Y1, i, n, s0, s1);
@@ -217,21 +243,8 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_tiles_kernel(LatticeDims
 
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
                                    const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
-  // Tiles where they measured faster: an FP64 E-vector with k = 2 or 4 (whole
-  // 64-lane tiles).  At 64^3 Q4 the gather takes 98.5 us against 117.5 in
-  // lattice order, at 48^3 Q2 10.5 against 11.2; with k = 3 or 7 (63-lane
-  // tiles) and for FP32 E-vectors lattice order is 5-27% faster.
-  const bool tiles = !fp32 && (d.k == 2 || d.k == 4);
-  if (tiles) {
-    GatherTiles g{};
-    g.th = (uint32_t)d.k;
-    g.tw = 64 / g.th;
-    g.ntx = ((uint32_t)d.Lx + g.tw - 1) / g.tw;
-    g.nty = ((uint32_t)d.Ly + g.th - 1) / g.th;
-    g.ntiles = g.ntx * g.nty * (uint32_t)d.Lz;
-    g.div_tw = make_fastdiv(g.tw);
-    g.div_ntx = make_fastdiv(g.ntx);
-    g.div_nplane = make_fastdiv(g.ntx * g.nty);
+  if (use_tiles(d, fp32)) {
+    const GatherTiles g = make_gather_tiles(d);
     const int64_t waves = ((int64_t)g.ntiles + kGatherUnroll - 1) / kGatherUnroll;
     const int nb = (int)((waves + kVecThreads / 64 - 1) / (kVecThreads / 64));
     if (fp32) {
@@ -478,9 +491,14 @@ __global__ __launch_bounds__(kGatherDotThreads) void gather_t_dot_kernel(const i
   if (threadIdx.x == 0) partial[blockIdx.x] = acc;
 }
 
-hipError_t launch_gather_t_dot(const LatticeDims* d, const int32_t* off, const int32_t* idx, const void* Y,
-                               bool fp32, const double* p, double* q, int64_t n, double* partial, hipStream_t s) {
+hipError_t launch_gather_t_dot(const LatticeDims& dims, bool csr, const int32_t* off, const int32_t* idx,
+                               const void* Y, bool fp32, const double* p, double* q, int64_t n, double* partial,
+                               hipStream_t s) {
+  // lattice order for both maps: the tiles of the plain gather measured no
+  // faster here (64^3 Q4 141.9 against 143.1 us) and slower at 48^3 Q2 (15.7
+  // against 13.5 us)
   const dim3 g(gather_dot_blocks(n)), b(kGatherDotThreads);
+  const LatticeDims* d = csr ? nullptr : &dims;
   if (d) {
     if (fp32)
       hipLaunchKernelGGL((gather_t_lattice_dot_kernel<float>), g, b, 0, s, *d, (const float*)Y, p, q, n, partial);
