@@ -159,8 +159,10 @@ def test_full_size_sampled_parity(name):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("w", [SMALL[1], SMALL[4], SMALL[6]], ids=["q2", "q3-curved", "q7-curved"])
+@pytest.mark.parametrize("w", [SMALL[1], SMALL[4], SMALL[5], SMALL[6]], ids=["q2", "q3-curved", "q4", "q7-curved"])
 def test_lattice_and_explicit_maps_bitwise_equal(w):
+    """The computed map (tiled G^T for FP64 at k = 2, 4; lattice order
+    otherwise) against the stored CSR map: bitwise equal applies and solves."""
     announce("map modes", w)
     prob, ora, inp = setup(w, oracle=False)
     u, v = dev(inp["u"]), dev(inp["v"])
