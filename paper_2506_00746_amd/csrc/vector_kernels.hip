@@ -241,8 +241,125 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_tiles_kernel(LatticeDims
   }
 }
 
+// G^T by element runs.  A lane takes the k DOFs I = k r + a (a < k) of one
+// lattice row (J, K): the nodes along x that element column r owns.  Each
+// candidate element's x-line holding them is one contiguous run of k
+// entries (wide loads); the DOF a = 0 also takes the entry a = k of element
+// r - 1.  A wavefront covers th = k rows (one element layer) times 64/k runs,
+// rows fastest, so the lanes of one run column read that element's adjacent
+// x-lines (contiguous in the E-vector) and each row's stores are contiguous.
+// Sums per DOF in ascending element order, absent candidates as +0 and a
+// final + 0: bitwise the explicit map's 0 + c_1 + c_2 + ...
+struct RunTiles {
+  uint32_t th, tr, ngr, nplane, ntiles;  // rows and runs per tile, run groups per row group, tiles per plane, total
+  FastDiv div_th, div_ngr, div_nplane;
+};
+
+template <class TE, bool TWO, int K>
+__global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims d, RunTiles g,
+                                                                    const TE* __restrict__ Y0,
+                                                                    const TE* __restrict__ Y1,
+                                                                    const double* __restrict__ bm,
+                                                                    double* __restrict__ out0,
+                                                                    double* __restrict__ out1) {
+  constexpr uint32_t D1 = K + 1, NE = D1 * D1 * D1;
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * (kVecThreads / 64) + (threadIdx.x >> 6);
+  const uint32_t rr = fastdiv(lane, g.div_th), dy = lane - rr * g.th;
+  const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * g.nplane;
+  const uint32_t m = fastdiv(rem, g.div_ngr), gr = rem - m * g.ngr;
+  const uint32_t nx = (uint32_t)d.nx, r = gr * g.tr + rr, J = m * g.th + dy;
+  if (t >= g.ntiles || rr >= g.tr || r > nx || J >= (uint32_t)d.Ly) return;  // no barrier below
+  const int64_t base = (int64_t)K * r + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz);
+  double s0[K], s1[K];
+#pragma unroll
+  for (int a = 0; a < K; ++a) s0[a] = s1[a] = 0.0;
+  if (J > 0 && J + 1 < (uint32_t)d.Ly && kz > 0 && kz + 1 < (uint32_t)d.Lz) {
+    const uint32_t iy = J / K, iz = kz / K, bi = J - K * iy, ci = kz - K * iz;
+    const bool ly = bi == 0, lz = ci == 0, up = r < nx, lo = r > 0 && r < nx;
+    TE run0[4][K], run1[4][K], low0[4], low1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {  // q = ty + 2 tz: candidate element rows in ascending order
+      const int ty = q & 1, tz = q >> 1;
+      const bool use = (ty || ly) && (tz || lz);
+      const uint32_t ey = iy - 1 + ty, ez = iz - 1 + tz;
+      const uint32_t line = ((ey + (uint32_t)d.ny * ez) * nx + r) * NE + D1 * ((J - K * ey) + D1 * (kz - K * ez));
+#pragma unroll
+      for (int a = 0; a < K; ++a) run0[q][a] = run1[q][a] = TE(0);
+      if (use && up) {
+        __builtin_memcpy(run0[q], Y0 + line, K * sizeof(TE));
+        if (TWO) __builtin_memcpy(run1[q], Y1 + line, K * sizeof(TE));
+      }
+      low0[q] = (use && lo) ? Y0[line - NE + K] : TE(0);  // element r - 1, entry a = k
+      low1[q] = (TWO && use && lo) ? Y1[line - NE + K] : TE(0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      s0[0] += (double)low0[q];
+      if (TWO) s1[0] += (double)low1[q];
+      if (lo) {  // a = 0 is interior in x only for 0 < r < nx
+        s0[0] += (double)run0[q][0];
+        if (TWO) s1[0] += (double)run1[q][0];
+      }
+#pragma unroll
+      for (int a = 1; a < K; ++a) {
+        s0[a] += (double)run0[q][a];
+        if (TWO) s1[a] += (double)run1[q][a];
+      }
+    }
+  }
+  const int na = r < nx ? K : 1;  // the last run holds only the boundary DOF I = Lx - 1
+#pragma unroll
+  for (int a = 0; a < K; ++a) {
+    if (a >= na) break;
+    double v = s0[a] + 0.0;
+    if (bm != nullptr) v -= bm[base + a];  // bm is 0 on Dirichlet DOFs
+    out0[base + a] = v;
+    if (TWO) out1[base + a] = s1[a] + 0.0;
+  }
+}
+
+template <class TE, bool TWO, int K>
+static void launch_runs(const LatticeDims& d, const void* Y0, const void* Y1, const double* bm, double* out0,
+                        double* out1, hipStream_t s) {
+  RunTiles g{};
+  g.th = K;
+  g.tr = 64 / K;
+  g.ngr = ((uint32_t)d.nx + 1 + g.tr - 1) / g.tr;
+  g.nplane = g.ngr * (((uint32_t)d.Ly + g.th - 1) / g.th);
+  g.ntiles = g.nplane * (uint32_t)d.Lz;
+  g.div_th = make_fastdiv(g.th);
+  g.div_ngr = make_fastdiv(g.ngr);
+  g.div_nplane = make_fastdiv(g.nplane);
+  const int nb = (int)(((int64_t)g.ntiles + kVecThreads / 64 - 1) / (kVecThreads / 64));
+  hipLaunchKernelGGL((gather_t_runs_kernel<TE, TWO, K>), dim3(nb), dim3(kVecThreads), 0, s, d, g, (const TE*)Y0,
+                     (const TE*)Y1, bm, out0, out1);
+}
+
+template <class TE, bool TWO>
+static bool launch_runs_k(const LatticeDims& d, const void* Y0, const void* Y1, const double* bm, double* out0,
+                          double* out1, hipStream_t s) {
+  switch (d.k) {
+    case 2: launch_runs<TE, TWO, 2>(d, Y0, Y1, bm, out0, out1, s); return true;
+    case 3: launch_runs<TE, TWO, 3>(d, Y0, Y1, bm, out0, out1, s); return true;
+    case 4: launch_runs<TE, TWO, 4>(d, Y0, Y1, bm, out0, out1, s); return true;
+    default: return false;
+  }
+}
+
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
                                    const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
+  // Per E-vector precision and order, the order measured fastest: runs for
+  // an FP32 E-vector at k = 2, 3, 4 (64^3 Q4 94.8 against 113-115 us in
+  // lattice order, 32^3 Q3 8.5 against 9.3-9.5, 48^3 Q2 10.1 against
+  // 10.6-10.8), tiles for FP64 at k = 2, 4 (runs: 127 us at 64^3 Q4), and
+  // lattice order for the rest (runs at 16^3 Q7: 12.6-12.7 against
+  // 8.2-10.7 us; at 32^3 Q3 FP64 8.4 against 7.7-8.0).
+  if (fp32) {
+    if (Y1 ? launch_runs_k<float, true>(d, Y0, Y1, bm, out0, out1, s)
+           : launch_runs_k<float, false>(d, Y0, nullptr, bm, out0, nullptr, s))
+      return hipGetLastError();
+  }
   if (use_tiles(d, fp32)) {
     const GatherTiles g = make_gather_tiles(d);
     const int64_t waves = ((int64_t)g.ntiles + kGatherUnroll - 1) / kGatherUnroll;
