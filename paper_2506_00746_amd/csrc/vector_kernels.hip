@@ -255,23 +255,13 @@ struct RunTiles {
   FastDiv div_th, div_ngr, div_nplane;
 };
 
+// The sums (before the final + 0) of the k DOFs of run r of row (J, K = kz):
+// candidates in ascending element order, absent ones as +0.
 template <class TE, bool TWO, int K>
-__global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims d, RunTiles g,
-                                                                    const TE* __restrict__ Y0,
-                                                                    const TE* __restrict__ Y1,
-                                                                    const double* __restrict__ bm,
-                                                                    double* __restrict__ out0,
-                                                                    double* __restrict__ out1) {
+__device__ __forceinline__ void run_sums(const LatticeDims& d, const TE* __restrict__ Y0, const TE* __restrict__ Y1,
+                                         uint32_t r, uint32_t J, uint32_t kz, double (&s0)[K], double (&s1)[K]) {
   constexpr uint32_t D1 = K + 1, NE = D1 * D1 * D1;
-  const uint32_t lane = threadIdx.x & 63;
-  const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * (kVecThreads / 64) + (threadIdx.x >> 6);
-  const uint32_t rr = fastdiv(lane, g.div_th), dy = lane - rr * g.th;
-  const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * g.nplane;
-  const uint32_t m = fastdiv(rem, g.div_ngr), gr = rem - m * g.ngr;
-  const uint32_t nx = (uint32_t)d.nx, r = gr * g.tr + rr, J = m * g.th + dy;
-  if (t >= g.ntiles || rr >= g.tr || r > nx || J >= (uint32_t)d.Ly) return;  // no barrier below
-  const int64_t base = (int64_t)K * r + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz);
-  double s0[K], s1[K];
+  const uint32_t nx = (uint32_t)d.nx;
 #pragma unroll
   for (int a = 0; a < K; ++a) s0[a] = s1[a] = 0.0;
   if (J > 0 && J + 1 < (uint32_t)d.Ly && kz > 0 && kz + 1 < (uint32_t)d.Lz) {
@@ -308,6 +298,25 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims 
       }
     }
   }
+}
+
+template <class TE, bool TWO, int K>
+__global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims d, RunTiles g,
+                                                                    const TE* __restrict__ Y0,
+                                                                    const TE* __restrict__ Y1,
+                                                                    const double* __restrict__ bm,
+                                                                    double* __restrict__ out0,
+                                                                    double* __restrict__ out1) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * (kVecThreads / 64) + (threadIdx.x >> 6);
+  const uint32_t rr = fastdiv(lane, g.div_th), dy = lane - rr * g.th;
+  const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * g.nplane;
+  const uint32_t m = fastdiv(rem, g.div_ngr), gr = rem - m * g.ngr;
+  const uint32_t nx = (uint32_t)d.nx, r = gr * g.tr + rr, J = m * g.th + dy;
+  if (t >= g.ntiles || rr >= g.tr || r > nx || J >= (uint32_t)d.Ly) return;  // no barrier below
+  const int64_t base = (int64_t)K * r + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz);
+  double s0[K], s1[K];
+  run_sums<TE, TWO, K>(d, Y0, Y1, r, J, kz, s0, s1);
   const int na = r < nx ? K : 1;  // the last run holds only the boundary DOF I = Lx - 1
 #pragma unroll
   for (int a = 0; a < K; ++a) {
@@ -319,18 +328,23 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims 
   }
 }
 
-template <class TE, bool TWO, int K>
-static void launch_runs(const LatticeDims& d, const void* Y0, const void* Y1, const double* bm, double* out0,
-                        double* out1, hipStream_t s) {
+static RunTiles make_run_tiles(const LatticeDims& d) {
   RunTiles g{};
-  g.th = K;
-  g.tr = 64 / K;
+  g.th = (uint32_t)d.k;
+  g.tr = 64 / g.th;
   g.ngr = ((uint32_t)d.nx + 1 + g.tr - 1) / g.tr;
   g.nplane = g.ngr * (((uint32_t)d.Ly + g.th - 1) / g.th);
   g.ntiles = g.nplane * (uint32_t)d.Lz;
   g.div_th = make_fastdiv(g.th);
   g.div_ngr = make_fastdiv(g.ngr);
   g.div_nplane = make_fastdiv(g.nplane);
+  return g;
+}
+
+template <class TE, bool TWO, int K>
+static void launch_runs(const LatticeDims& d, const void* Y0, const void* Y1, const double* bm, double* out0,
+                        double* out1, hipStream_t s) {
+  const RunTiles g = make_run_tiles(d);
   const int nb = (int)(((int64_t)g.ntiles + kVecThreads / 64 - 1) / (kVecThreads / 64));
   hipLaunchKernelGGL((gather_t_runs_kernel<TE, TWO, K>), dim3(nb), dim3(kVecThreads), 0, s, d, g, (const TE*)Y0,
                      (const TE*)Y1, bm, out0, out1);
@@ -611,9 +625,11 @@ __global__ __launch_bounds__(kGatherDotThreads) void gather_t_dot_kernel(const i
 hipError_t launch_gather_t_dot(const LatticeDims& dims, bool csr, const int32_t* off, const int32_t* idx,
                                const void* Y, bool fp32, const double* p, double* q, int64_t n, double* partial,
                                hipStream_t s) {
-  // lattice order for both maps: the tiles of the plain gather measured no
-  // faster here (64^3 Q4 141.9 against 143.1 us) and slower at 48^3 Q2 (15.7
-  // against 13.5 us)
+  // lattice order for both maps and precisions: the tiles of the plain FP64
+  // gather measured no faster here (64^3 Q4 141.9 against 143.1 us, 48^3 Q2
+  // 15.7 against 13.5), and its element runs for FP32 slower (64^3 Q4 190
+  // against 145 us, 32^3 Q3 16.1 against 11.8, 48^3 Q2 16.6 against 13.3):
+  // this kernel's fixed grid leaves 1-2 tiles per wavefront.
   const dim3 g(gather_dot_blocks(n)), b(kGatherDotThreads);
   const LatticeDims* d = csr ? nullptr : &dims;
   if (d) {
