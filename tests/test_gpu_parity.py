@@ -171,7 +171,9 @@ def test_lattice_and_explicit_maps_bitwise_equal(w):
         prob.set_map_mode(mode)
         r, jv = prob.residual_and_jvp(u, v)
         rm = prob.residual(u, prec="mixed")
-        outs[mode] = [host(r), host(jv), host(rm), host(prob.jacobian_apply(u, v))]
+        rm2, jvm2 = prob.residual_and_jvp(u, v, prec="mixed")  # two FP32 E-vectors at once
+        outs[mode] = [host(r), host(jv), host(rm), host(prob.jacobian_apply(u, v)), host(rm2), host(jvm2),
+                      host(prob.jacobian_apply(u, v, prec="mixed"))]
     for a, b in zip(outs["lattice"], outs["explicit"]):
         assert np.array_equal(a, b)
     # the CG solves (fused G^T + p.q) give bitwise the same iterates too
