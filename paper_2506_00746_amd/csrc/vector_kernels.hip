@@ -142,10 +142,12 @@ __device__ __forceinline__ void lattice_rows_sum(const LatticeDims& d, const TE*
   }
 }
 
-// DOFs per thread of the plain lattice gather.  Two measured best: at 64^3
-// Q4 the FP64 gather takes 120 us against 124 with one DOF per thread (FP32
-// E-vector 115 against 127); four gain nothing.
-constexpr int kGatherUnroll = 2;
+// DOFs (tiles) per thread of the plain lattice and tiled gathers.  One
+// measured best with the current orders: the 64^3 Q4 FP64 tiled gather takes
+// 94.8 us against 98.7 with two and 99.2 with four, 48^3 Q2 10.3 against
+// 10.7 and 10.8, the 16^3 Q7 FP32 lattice gather 9.9 against 10.6 and 14.6
+// (in lattice order alone two had been best: 64^3 Q4 120 against 124 us).
+constexpr int kGatherUnroll = 1;
 
 template <class TE, bool TWO>
 __global__ __launch_bounds__(kVecThreads) void gather_t_lattice_kernel(LatticeDims d, const TE* __restrict__ Y0,
