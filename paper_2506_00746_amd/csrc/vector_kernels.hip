@@ -319,14 +319,25 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims 
   const int64_t base = (int64_t)K * r + (int64_t)d.Lx * ((int64_t)J + (int64_t)d.Ly * kz);
   double s0[K], s1[K];
   run_sums<TE, TWO, K>(d, Y0, Y1, r, J, kz, s0, s1);
-  const int na = r < nx ? K : 1;  // the last run holds only the boundary DOF I = Lx - 1
+  // A full run is stored with wide stores (2 x 16 bytes per lane at k = 4):
+  // per DOF stores left each instruction 8 of every 32 bytes of the lines it
+  // touched, and cost 64^3 Q4 94 against 82 us.
+  if (r < nx) {
+    double v0[K], v1[K], b[K];
+    if (bm != nullptr) __builtin_memcpy(b, bm + base, sizeof b);
 #pragma unroll
-  for (int a = 0; a < K; ++a) {
-    if (a >= na) break;
-    double v = s0[a] + 0.0;
-    if (bm != nullptr) v -= bm[base + a];  // bm is 0 on Dirichlet DOFs
-    out0[base + a] = v;
-    if (TWO) out1[base + a] = s1[a] + 0.0;
+    for (int a = 0; a < K; ++a) {
+      v0[a] = s0[a] + 0.0;
+      if (bm != nullptr) v0[a] -= b[a];  // bm is 0 on Dirichlet DOFs
+      v1[a] = s1[a] + 0.0;
+    }
+    __builtin_memcpy(out0 + base, v0, sizeof v0);
+    if (TWO) __builtin_memcpy(out1 + base, v1, sizeof v1);
+  } else {  // the last run holds only the boundary DOF I = Lx - 1
+    double v = s0[0] + 0.0;
+    if (bm != nullptr) v -= bm[base];
+    out0[base] = v;
+    if (TWO) out1[base] = s1[0] + 0.0;
   }
 }
 
@@ -366,7 +377,7 @@ static bool launch_runs_k(const LatticeDims& d, const void* Y0, const void* Y1, 
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
                                    const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
   // Per E-vector precision and order, the order measured fastest: runs for
-  // an FP32 E-vector at k = 2, 3, 4 (64^3 Q4 94.8 against 113-115 us in
+  // an FP32 E-vector at k = 2, 3, 4 (64^3 Q4 80-82 against 113-115 us in
   // lattice order, 32^3 Q3 8.5 against 9.3-9.5, 48^3 Q2 10.1 against
   // 10.6-10.8), tiles for FP64 at k = 2, 4 (runs: 127 us at 64^3 Q4), and
   // lattice order for the rest (runs at 16^3 Q7: 12.6-12.7 against
