@@ -267,14 +267,29 @@ __device__ __forceinline__ void gather_line(const ElemParams& P, const double* c
     const bool row = J > 0 && J < P.Ly - 1 && K > 0 && K < P.Lz - 1;
     const int64_t base = I0 + (int64_t)P.Lx * (J + (int64_t)P.Ly * K);
     // every node of a valid element lies in the lattice: load unconditionally
-    // (no branch per load) and zero the Dirichlet ones
+    // (no branch per load) and zero the Dirichlet ones.  FP64 kernels read
+    // the line's D1 contiguous DOFs with wide loads (48^3 Q2 element kernel
+    // -2%, 16^3 Q7 -1.3%, 64^3 Q4 -0.4%); FP32 ones one DOF per load (wide
+    // loads cost 64^3 Q4 +3% there).
+    if constexpr (sizeof(T) == 8) {
+      double raw[NG][D1];
 #pragma unroll
-    for (int a = 0; a < D1; ++a) {
-      const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
+      for (int f = 0; f < NG; ++f) __builtin_memcpy(raw[f], src[f] + base, sizeof raw[f]);
 #pragma unroll
-      for (int f = 0; f < NG; ++f) {
-        const double val = src[f][base + a];
-        in[f][a] = ok ? (T)val : T(0);
+      for (int a = 0; a < D1; ++a) {
+        const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) in[f][a] = ok ? (T)raw[f][a] : T(0);
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < D1; ++a) {
+        const bool ok = row && I0 + a > 0 && I0 + a < P.Lx - 1;
+#pragma unroll
+        for (int f = 0; f < NG; ++f) {
+          const double val = src[f][base + a];
+          in[f][a] = ok ? (T)val : T(0);
+        }
       }
     }
   } else {
