@@ -182,15 +182,16 @@ struct Config {
   // Jacobian kernel in 67 VGPRs (7 waves), 15% faster.  Q3 / nq 5 in FP64: 5
   // fits it in 95 VGPRs without spills (5 waves instead of 4).
   static constexpr int WPE = (D1 == 5 && NQ == 6 && sizeof(T) == 4) ? 6 : ((D1 == 4 && NQ == 5 && sizeof(T) == 8) ? 5 : 1);
-  // RU, RUQ: unroll factors of the runtime loops of high-order kernels
-  static constexpr int RU = 1, RUQ = 1;
+  // RU: unroll factor of the runtime loops of high-order kernels
+  static constexpr int RU = 1;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
-  // The runtime loops over node rows (RU, 8 iterations) and points (RUQ, 9)
-  // are unrolled by 2 and 3: each iteration waits for its table slice (scalar
-  // loads) and LDS reads, and two or three in flight hide that wait at the
-  // two waves per SIMD these kernels run at.  Fully unrolled they spill.
-  static constexpr int RU = 2, RUQ = 3;
+  // The runtime loops of phases C and D (over node rows, 8 iterations) are
+  // unrolled by 2: each iteration waits for its table slice (scalar loads)
+  // and LDS reads, and two in flight hide that wait at the two waves per SIMD
+  // these kernels run at.  Fully unrolled (even-odd) they spill; the x-pass
+  // and x-back, outside the register peak, are even-odd at every order.
+  static constexpr int RU = 2;
   static constexpr int NT = 256;
   static constexpr int EB = 3;
   static constexpr bool SEQ = true;
@@ -306,29 +307,18 @@ __device__ __forceinline__ void gather_line(const ElemParams& P, const double* c
 template <int D1, int NQ, int XQ, class T, class TB>
 __device__ __forceinline__ void xpass_line(const TB& tb, const T (&in)[D1], T* x) {
   constexpr int XS = D1 * NQ * XQ;
-  if constexpr (Unroll<D1>::full) {
-    // even-odd form
-    T e[EO<D1, NQ>::AP], o[EO<D1, NQ>::AH], y0[NQ], y1[NQ];
-    eo_split<D1, NQ>(in, e, o);
-    eo_forward<D1, NQ, true>(tb.Pb, tb.Nb, e, o, y0);
-    eo_forward<D1, NQ, false>(tb.Px, tb.Nx, e, o, y1);
+  // even-odd form at every order: its tables are read once per line, and at
+  // Q7 it runs the 16^3 Jacobian kernel (with the x-back below) in 54.9
+  // against 57.4 us with runtime loops over the full tables (FP32 33.5 against
+  // 35.8), registers unchanged
+  T e[EO<D1, NQ>::AP], o[EO<D1, NQ>::AH], y0[NQ], y1[NQ];
+  eo_split<D1, NQ>(in, e, o);
+  eo_forward<D1, NQ, true>(tb.Pb, tb.Nb, e, o, y0);
+  eo_forward<D1, NQ, false>(tb.Px, tb.Nx, e, o, y1);
 #pragma unroll
-    for (int qx = 0; qx < NQ; ++qx) {
-      x[qx * XQ] = y0[qx];
-      x[XS + qx * XQ] = y1[qx];
-    }
-  } else {  // high order: full tables, runtime loop (bounded register use)
-#pragma unroll(Unroll<NQ>::full ? NQ : Config<D1, NQ, T>::RUQ)
-    for (int qx = 0; qx < NQ; ++qx) {
-      T s0 = tb.B[qx * D1] * in[0], s1 = tb.Dx[qx * D1] * in[0];
-#pragma unroll
-      for (int a = 1; a < D1; ++a) {
-        s0 += tb.B[qx * D1 + a] * in[a];
-        s1 += tb.Dx[qx * D1 + a] * in[a];
-      }
-      x[qx * XQ] = s0;
-      x[XS + qx * XQ] = s1;
-    }
+  for (int qx = 0; qx < NQ; ++qx) {
+    x[qx * XQ] = y0[qx];
+    x[XS + qx * XQ] = y1[qx];
   }
 }
 
@@ -937,21 +927,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
       }
       // output 0 is the JVP (or residual); output 1 the residual of residual + JVP
       T* out = static_cast<T*>(o == 0 ? (OP == OP_RESJVP ? P.out1 : P.out0) : P.out0) + pos;
-      if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
-#pragma unroll(Config<D1, NQ, T>::RU)
-        for (int a = 0; a < D1; ++a) {
-          T s = tb.Dx[a] * k0[0];
-          s += tb.B[a] * k1[0];
-#pragma unroll
-          for (int qx = 1; qx < NQ; ++qx) {
-            s += tb.Dx[qx * D1 + a] * k0[qx];
-            s += tb.B[qx * D1 + a] * k1[qx];
-          }
-          out[a * OSTR] = s;
-        }
-        continue;
-      }
-      // out = Dx^T K0 + B^T K1 (even-odd form, one sum for both)
+      // out = Dx^T K0 + B^T K1 (even-odd form at every order, one sum for both)
       using E = EO<D1, NQ>;
       T xe[E::QH + 1], xo[E::QH + 1], xm, sp[E::AP], sm[E::AH], y[D1];
 #pragma unroll
