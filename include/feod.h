@@ -129,8 +129,8 @@ typedef struct {
  * measured within 2.5% of the fused Jacobian action over whole Newton solves
  * on both (29.8 vs 30.5 ms and 38.8 vs 38.2 ms), so the default keeps the
  * fused action, whose quadrature data never leaves the registers.  At Q7 it
- * pays: the curved 16^3 Q7 Newton solve takes 100.0 instead of 110.7 ms and
- * its adjoint gradient 58.0 instead of 64.1 ms (FP64), so set it for Q6+. */
+ * pays: the curved 16^3 Q7 Newton solve takes 95.4 instead of 104.8 ms and
+ * its adjoint gradient 55.3 instead of 60.6 ms (FP64), so set it for Q6+. */
 void feod_default_opts(feod_solver_opts* opts);
 
 /* Build the mesh, element-to-DOF map G, transposed map for G^T, 1D tables and

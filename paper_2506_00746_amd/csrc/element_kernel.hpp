@@ -186,11 +186,12 @@ struct Config {
   static constexpr int RU = 1;
 };
 template <class T> struct Config<8, 9, T> {  // 81 lines: 3 elements on 4 wavefronts
-  // The runtime loops of phases C and D (over node rows, 8 iterations) are
-  // unrolled by 2: each iteration waits for its table slice (scalar loads)
-  // and LDS reads, and two in flight hide that wait at the two waves per SIMD
-  // these kernels run at.  Fully unrolled (even-odd) they spill; the x-pass
-  // and x-back, outside the register peak, are even-odd at every order.
+  // The runtime loops of phases C and D (the forward z-pass over node rows,
+  // the z-back and y-back over output node pairs, even-odd) are unrolled by
+  // 2: each iteration waits for its table slice (scalar loads) and LDS
+  // reads, and two in flight hide that wait at the two waves per SIMD these
+  // kernels run at.  Fully unrolled they spill; the x-pass and x-back,
+  // outside the register peak, are fully unrolled even-odd at every order.
   static constexpr int RU = 2;
   static constexpr int NT = 256;
   static constexpr int EB = 3;
@@ -749,19 +750,40 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         T* h = Hs + el * L::HSTR + o * 3 * D1 * NQ2 + qxy;
-        if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
+        if constexpr (!Unroll<D1>::full) {  // high order: even-odd, runtime loop over output pairs
+          static_assert(D1 % 2 == 0, "the runtime even-odd loops take node pairs");
+          T xe0[E::QH + 1], xo0[E::QH + 1], xm0, xe1[E::QH + 1], xo1[E::QH + 1], xm1, xe2[E::QH + 1],
+              xo2[E::QH + 1], xm2;
+          eo_pairs<D1, NQ>(g[o][0], xe0, xo0, xm0);
+          eo_pairs<D1, NQ>(g[o][1], xe1, xo1, xm1);
+          eo_pairs<D1, NQ>(g[o][2], xe2, xo2, xm2);
 #pragma unroll(Config<D1, NQ, T>::RU)
-          for (int c = 0; c < D1; ++c) {
-            T s0 = tb.B[c] * g[o][0][0], s1 = tb.B[c] * g[o][1][0], s2 = tb.Dz[c] * g[o][2][0];
+          for (int a = 0; a < E::AH; ++a) {
+            T sp0 = tb.Pb[a] * xe0[0], sm0 = tb.Nb[a] * xo0[0];
+            T sp1 = tb.Pb[a] * xe1[0], sm1 = tb.Nb[a] * xo1[0];
+            T sp2 = tb.Pz[a] * xo2[0], sm2 = tb.Nz[a] * xe2[0];
 #pragma unroll
-            for (int qz = 1; qz < NQ; ++qz) {
-              s0 += tb.B[qz * D1 + c] * g[o][0][qz];
-              s1 += tb.B[qz * D1 + c] * g[o][1][qz];
-              s2 += tb.Dz[qz * D1 + c] * g[o][2][qz];
+            for (int q = 1; q < E::QH; ++q) {
+              const T pb = tb.Pb[q * E::AP + a], nb = tb.Nb[q * E::AH + a];
+              sp0 += pb * xe0[q];
+              sm0 += nb * xo0[q];
+              sp1 += pb * xe1[q];
+              sm1 += nb * xo1[q];
+              sp2 += tb.Pz[q * E::AP + a] * xo2[q];
+              sm2 += tb.Nz[q * E::AH + a] * xe2[q];
             }
-            h[c * NQ2] = s0;
-            h[D1 * NQ2 + c * NQ2] = s1;
-            h[2 * D1 * NQ2 + c * NQ2] = s2;
+            if constexpr (NQ % 2) {  // the middle point
+              const T pm = tb.Pb[E::QH * E::AP + a];
+              sp0 += pm * xm0;
+              sp1 += pm * xm1;
+              sm2 += tb.Nz[E::QH * E::AH + a] * xm2;
+            }
+            h[a * NQ2] = sp0 + sm0;
+            h[(D1 - 1 - a) * NQ2] = sp0 - sm0;
+            h[(D1 + a) * NQ2] = sp1 + sm1;
+            h[(2 * D1 - 1 - a) * NQ2] = sp1 - sm1;
+            h[(2 * D1 + a) * NQ2] = sp2 + sm2;
+            h[(3 * D1 - 1 - a) * NQ2] = sp2 - sm2;
           }
           continue;
         }
@@ -840,22 +862,38 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
 #pragma unroll
         for (int o = 0; o < O; ++o) {
           T* k = Xs + el * L::XSTR + o * 2 * L::XS + (c * NQ + qx) * L::XQ;
-          if constexpr (!Unroll<D1>::full) {  // high order: full tables, runtime loop
-            const T(&h0)[NQ] = hv[3 * o];
-            const T(&h1)[NQ] = hv[3 * o + 1];
-            const T(&h2)[NQ] = hv[3 * o + 2];
+          if constexpr (!Unroll<D1>::full) {  // high order: even-odd, runtime loop over output pairs
+            static_assert(D1 % 2 == 0, "the runtime even-odd loops take node pairs");
+            T xe0[E::QH + 1], xo0[E::QH + 1], xm0, xe1[E::QH + 1], xo1[E::QH + 1], xm1, xe2[E::QH + 1],
+                xo2[E::QH + 1], xm2;
+            eo_pairs<D1, NQ>(hv[3 * o], xe0, xo0, xm0);
+            eo_pairs<D1, NQ>(hv[3 * o + 1], xe1, xo1, xm1);
+            eo_pairs<D1, NQ>(hv[3 * o + 2], xe2, xo2, xm2);
 #pragma unroll(Config<D1, NQ, T>::RU)
-            for (int b = 0; b < D1; ++b) {
-              T s0 = tb.B[b] * h0[0], s1 = tb.Dy[b] * h1[0];
-              s1 += tb.B[b] * h2[0];
+            for (int a = 0; a < E::AH; ++a) {
+              T sp0 = tb.Pb[a] * xe0[0], sm0 = tb.Nb[a] * xo0[0];
+              T sp1 = tb.Py[a] * xo1[0], sm1 = tb.Ny[a] * xe1[0];
+              sp1 += tb.Pb[a] * xe2[0];
+              sm1 += tb.Nb[a] * xo2[0];
 #pragma unroll
-              for (int qy = 1; qy < NQ; ++qy) {
-                s0 += tb.B[qy * D1 + b] * h0[qy];
-                s1 += tb.Dy[qy * D1 + b] * h1[qy];
-                s1 += tb.B[qy * D1 + b] * h2[qy];
+              for (int q = 1; q < E::QH; ++q) {
+                const T pb = tb.Pb[q * E::AP + a], nb = tb.Nb[q * E::AH + a];
+                sp0 += pb * xe0[q];
+                sm0 += nb * xo0[q];
+                sp1 += tb.Py[q * E::AP + a] * xo1[q];
+                sm1 += tb.Ny[q * E::AH + a] * xe1[q];
+                sp1 += pb * xe2[q];
+                sm1 += nb * xo2[q];
               }
-              k[b] = s0;
-              k[L::XS + b] = s1;
+              if constexpr (NQ % 2) {  // the middle point
+                sp0 += tb.Pb[E::QH * E::AP + a] * xm0;
+                sm1 += tb.Ny[E::QH * E::AH + a] * xm1;
+                sp1 += tb.Pb[E::QH * E::AP + a] * xm2;
+              }
+              k[a] = sp0 + sm0;
+              k[D1 - 1 - a] = sp0 - sm0;
+              k[L::XS + a] = sp1 + sm1;
+              k[L::XS + D1 - 1 - a] = sp1 - sm1;
             }
             continue;
           }
