@@ -627,7 +627,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
         adj[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
         adj[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
         det = J[0][0] * adj[0][0] + J[0][1] * adj[1][0] + J[0][2] * adj[2][0];
-        const T inv_det = T(1) / det;
+        const T inv_det = fe_rcp(det);
         // physical gradient g = Jg^{-T} ghat = adj^T ghat / det
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -660,7 +660,7 @@ void element_kernel(ElemParams P, Tab<D1, NQ, T> tb) {
         T Ch[3][3];
         const T s = rho * w3;
         if (CURVED) {
-          const T sd = s / det;
+          const T sd = s * fe_rcp(det);
           T AT[3][3];  // adj Tm
 #pragma unroll
           for (int i = 0; i < 3; ++i)

@@ -24,6 +24,20 @@ __device__ __forceinline__ double fe_rsqrt(double x) {
 }
 __device__ __forceinline__ float fe_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// 1/x: the hardware reciprocal refined by Newton steps on f(y) = 1/y - x
+// (y <- y + y (1 - x y)), two for FP64, one for FP32.  Within about an ulp,
+// and a third of the instructions of a correctly rounded division.
+__device__ __forceinline__ double fe_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  y = __builtin_fma(y, __builtin_fma(-x, y, 1.0), y);
+  return y;
+}
+__device__ __forceinline__ float fe_rcp(float x) {
+  const float y = __builtin_amdgcn_rcpf(x);
+  return __builtin_fmaf(y, __builtin_fmaf(-x, y, 1.0f), y);
+}
+
 // a^r and, for dual numbers, d(a^r) = r a^(r-1) da, without divisions:
 //   r = 1/2:  a^r = a t, t = a^(-1/2);  d = t da / 2
 //   r = 1/4:  a^r = s u, s = a t, u = s^(-1/2);  d = a^r t^2 da / 4
