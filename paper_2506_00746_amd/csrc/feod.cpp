@@ -353,8 +353,8 @@ feod_status gather_t_dot(feod_ctx* c, bool fp32, const double* p, double* q) {
 
 // Preconditioned CG (Jacobi when dinv != null).  One iteration is four
 // launches: the element kernel on p, G^T fused with the p.q partial sums, the
-// step (alpha, x, r, z and the r.z / r.r partials) and the new direction
-// (beta, p).  Inner products stay on the device as fixed-order partial sums;
+// step (alpha, r, z and the r.z / r.r partials) and the new direction (x +=
+// alpha p, then beta and p; x and p are read once).  Inner products stay on the device as fixed-order partial sums;
 // the host reads them every check_every iterations.  J applies use the fused
 // kernel at u, or (pa) the stored partial-assembly data of u in precision prec
 // (set up by the caller).
@@ -414,11 +414,20 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
     else
       TRY(run_element(c, OP_JVP, prec, params(c, u, p, c->d_Y0, nullptr, prec, p_override)));
     TRY(gather_t_dot(c, prec == 1, p, q));
+    const int n_pq = gather_dot_blocks(N);
     TRY(timed(c, "cg_step", [&] {
-      return launch_cg_step(x, r, z, p, q, dinv, c->cg_part(cur), c->cg_part(C_PQ), gather_dot_blocks(N), N,
-                            c->cg_part(nxt),
+      return launch_cg_step(r, z, q, dinv, c->cg_part(cur), c->cg_part(C_PQ), n_pq, N, c->cg_part(nxt),
                             c->cg_part(C_RR), c->d_sc, S_RZ, S_PQ, c->stream);
     }));
+    // x += alpha p of this step, where the direction kernel cannot do it
+    // (CG stops, or its residual is replaced from x, right after the step)
+    bool x_done = false;
+    auto update_x = [&]() -> feod_status {
+      x_done = true;
+      return timed(c, "cg_x_update", [&] {
+        return launch_cg_x_update(x, p, c->cg_part(cur), c->cg_part(C_PQ), n_pq, N, c->stream);
+      });
+    };
     out->iters = it + 1;
     if ((it + 1) % check_every == 0 || it + 1 == max_it) {
       double rr, pq;
@@ -430,6 +439,7 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
       out->res = std::sqrt(rr);
       if (reliable && (out->res <= tol || out->res <= kReliableDrop * last_true)) {
         // q is free here (consumed by the step): q = J64 x, then r = b - q
+        TRY(update_x());
         TRY(apply_jvp(c, u, x, q, nullptr, 0, p_override));
         TRY(timed(c, "cg_true_residual", [&] {
           return launch_cg_true_residual(r, z, b, q, dinv, N, c->cg_part(nxt), c->cg_part(C_RR), c->stream);
@@ -438,10 +448,15 @@ feod_status cg(feod_ctx* c, const double* u, const double* b, double* x, double 
         TRY(read_rr(nxt, &rr, &pq));
         out->res = last_true = std::sqrt(rr);
       }
-      if (out->res <= tol) return FEOD_OK;
+      if (out->res <= tol) {
+        if (!x_done) TRY(update_x());
+        return FEOD_OK;
+      }
     }
-    TRY(timed(c, "cg_direction",
-              [&] { return launch_cg_direction(p, z, c->cg_part(nxt), c->cg_part(cur), N, c->stream); }));
+    TRY(timed(c, "cg_direction", [&] {
+      return launch_cg_direction(p, z, x_done ? nullptr : x, c->cg_part(nxt), c->cg_part(cur), c->cg_part(C_PQ),
+                                 n_pq, N, c->stream);
+    }));
     std::swap(cur, nxt);
   }
   out->status = FEOD_ENOCONV;

@@ -146,15 +146,19 @@ hipError_t launch_cg_init(double* x, double* r, double* z, double* p, const doub
 hipError_t launch_cg_true_residual(double* r, double* z, const double* b, const double* jx, const double* dinv,
                                    int64_t n, double* part_rz, double* part_rr, hipStream_t s);
 // alpha = sum(part_rz)/sum(part_pq) (n_pq partials of p.q from the gather);
-// x += alpha p; r -= alpha q; z = dinv r; new partials of r.z (part_rz_new)
-// and r.r (part_rr, when dinv); block 0 stores the two totals in sc[i_rz],
-// sc[i_pq].
-hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
-                          const double* part_rz, const double* part_pq, int n_pq, int64_t n, double* part_rz_new,
-                          double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s);
-// beta = sum(part_new)/sum(part_old); p = z + beta p
-hipError_t launch_cg_direction(double* p, const double* z, const double* part_new, const double* part_old,
-                               int64_t n, hipStream_t s);
+// r -= alpha q; z = dinv r; new partials of r.z (part_rz_new) and r.r
+// (part_rr, when dinv); block 0 stores the two totals in sc[i_rz], sc[i_pq].
+// x is left to launch_cg_direction or launch_cg_x_update.
+hipError_t launch_cg_step(double* r, double* z, const double* q, const double* dinv, const double* part_rz,
+                          const double* part_pq, int n_pq, int64_t n, double* part_rz_new, double* part_rr,
+                          double* sc, int i_rz, int i_pq, hipStream_t s);
+// beta = sum(part_new)/sum(part_old); x (unless null) += alpha p with the
+// step's alpha = sum(part_old)/sum(part_pq); then p = z + beta p
+hipError_t launch_cg_direction(double* p, const double* z, double* x, const double* part_new,
+                               const double* part_old, const double* part_pq, int n_pq, int64_t n, hipStream_t s);
+// x += alpha p, alpha = sum(part_rz)/sum(part_pq): the last step's update of x
+hipError_t launch_cg_x_update(double* x, const double* p, const double* part_rz, const double* part_pq, int n_pq,
+                              int64_t n, hipStream_t s);
 // y = a*x + b*y with host scalars; x or y may alias out
 hipError_t launch_axpby(double* out, double a, const double* x, double b, const double* y,
                         int64_t n, hipStream_t s);

@@ -742,12 +742,13 @@ hipError_t launch_cg_true_residual(double* r, double* z, const double* b, const 
   return hipGetLastError();
 }
 
-// alpha = (r.z) / (p.q) from the partials; x += alpha p; r -= alpha q;
-// z = dinv r; new partials of r.z and r.r.  Block 0 records r.z and p.q in
-// sc[i_rz], sc[i_pq] for the host's convergence and breakdown checks.
+// alpha = (r.z) / (p.q) from the partials; r -= alpha q; z = dinv r; new
+// partials of r.z and r.r.  x is not touched here: x += alpha p happens in
+// the direction kernel (which reads p anyway) or, when CG stops or replaces
+// its residual after this step, in cg_x_update.  Block 0 records r.z and p.q
+// in sc[i_rz], sc[i_pq] for the host's convergence and breakdown checks.
 template <bool PREC>
-__global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict__ x, double* __restrict__ r,
-                                                             double* __restrict__ z, const double* __restrict__ p,
+__global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict__ r, double* __restrict__ z,
                                                              const double* __restrict__ q,
                                                              const double* __restrict__ dinv,
                                                              const double* __restrict__ part_rz,
@@ -759,13 +760,11 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
   const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
   const int64_t first = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
   // the first pass's loads go out before the scalar sums, hiding their latency
-  double xv[kCgUnroll], pv[kCgUnroll], rv[kCgUnroll], qv[kCgUnroll], dv[kCgUnroll];
+  double rv[kCgUnroll], qv[kCgUnroll], dv[kCgUnroll];
   auto load = [&](int64_t i0) {
 #pragma unroll
     for (int u = 0; u < kCgUnroll; ++u) {
       const int64_t i = min(i0 + u * stride, n - 1);
-      xv[u] = x[i];
-      pv[u] = p[i];
       rv[u] = r[i];
       qv[u] = q[i];
       if (PREC) dv[u] = dinv[i];
@@ -785,7 +784,6 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
     for (int u = 0; u < kCgUnroll; ++u) {
       const int64_t i = i0 + u * stride;
       if (i < n) {
-        x[i] = xv[u] + alpha * pv[u];
         const double ri = rv[u] - alpha * qv[u];
         r[i] = ri;
         if (PREC) {
@@ -807,50 +805,88 @@ __global__ __launch_bounds__(kCgThreads) void cg_step_kernel(double* __restrict_
   }
 }
 
-hipError_t launch_cg_step(double* x, double* r, double* z, const double* p, const double* q, const double* dinv,
-                          const double* part_rz, const double* part_pq, int n_pq, int64_t n, double* part_rz_new,
-                          double* part_rr, double* sc, int i_rz, int i_pq, hipStream_t s) {
+hipError_t launch_cg_step(double* r, double* z, const double* q, const double* dinv, const double* part_rz,
+                          const double* part_pq, int n_pq, int64_t n, double* part_rz_new, double* part_rr,
+                          double* sc, int i_rz, int i_pq, hipStream_t s) {
   if (dinv)
-    hipLaunchKernelGGL(cg_step_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, z, p, q, dinv, part_rz,
+    hipLaunchKernelGGL(cg_step_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, r, z, q, dinv, part_rz,
                        part_pq, n_pq, n, part_rz_new, part_rr, sc, i_rz, i_pq);
   else
-    hipLaunchKernelGGL(cg_step_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, r, r, p, q, nullptr,
-                       part_rz, part_pq, n_pq, n, part_rz_new, nullptr, sc, i_rz, i_pq);
+    hipLaunchKernelGGL(cg_step_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, r, r, q, nullptr, part_rz,
+                       part_pq, n_pq, n, part_rz_new, nullptr, sc, i_rz, i_pq);
   return hipGetLastError();
 }
 
-// beta = (r.z)_new / (r.z)_old from the partials; p = z + beta p.
+// beta = (r.z)_new / (r.z)_old from the partials; with x: x += alpha p (the
+// step's alpha = (r.z)_old / (p.q), the same expression and partial sums as
+// the step uses) before p = z + beta p.
+template <bool XUPD>
 __global__ __launch_bounds__(kCgThreads) void cg_direction_kernel(double* __restrict__ p,
                                                                   const double* __restrict__ z,
+                                                                  double* __restrict__ x,
                                                                   const double* __restrict__ part_new,
-                                                                  const double* __restrict__ part_old, int64_t n) {
+                                                                  const double* __restrict__ part_old,
+                                                                  const double* __restrict__ part_pq, int n_pq,
+                                                                  int64_t n) {
   __shared__ double ws[kCgThreads / 64];
   const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
   const int64_t first = (int64_t)blockIdx.x * kCgThreads + threadIdx.x;
-  double zv[kCgUnroll], pv[kCgUnroll];
+  double zv[kCgUnroll], pv[kCgUnroll], xv[kCgUnroll];
   auto load = [&](int64_t i0) {
 #pragma unroll
     for (int u = 0; u < kCgUnroll; ++u) {
       const int64_t i = min(i0 + u * stride, n - 1);
       zv[u] = z[i];
       pv[u] = p[i];
+      if (XUPD) xv[u] = x[i];
     }
   };
   if (first < n) load(first);
-  const double beta = cg_total(part_new, ws) / cg_total(part_old, ws);
+  const double rz_old = cg_total(part_old, ws);
+  const double beta = cg_total(part_new, ws) / rz_old;
+  const double alpha = XUPD ? rz_old / cg_total(part_pq, ws, n_pq) : 0.0;
   for (int64_t i0 = first; i0 < n; i0 += kCgUnroll * stride) {
     if (i0 != first) load(i0);
 #pragma unroll
     for (int u = 0; u < kCgUnroll; ++u) {
       const int64_t i = i0 + u * stride;
-      if (i < n) p[i] = zv[u] + beta * pv[u];
+      if (i < n) {
+        if (XUPD) x[i] = xv[u] + alpha * pv[u];
+        p[i] = zv[u] + beta * pv[u];
+      }
     }
   }
 }
 
-hipError_t launch_cg_direction(double* p, const double* z, const double* part_new, const double* part_old,
-                               int64_t n, hipStream_t s) {
-  hipLaunchKernelGGL(cg_direction_kernel, dim3(kCgBlocks), dim3(kCgThreads), 0, s, p, z, part_new, part_old, n);
+hipError_t launch_cg_direction(double* p, const double* z, double* x, const double* part_new,
+                               const double* part_old, const double* part_pq, int n_pq, int64_t n, hipStream_t s) {
+  if (x)
+    hipLaunchKernelGGL(cg_direction_kernel<true>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, p, z, x, part_new,
+                       part_old, part_pq, n_pq, n);
+  else
+    hipLaunchKernelGGL(cg_direction_kernel<false>, dim3(kCgBlocks), dim3(kCgThreads), 0, s, p, z, nullptr,
+                       part_new, part_old, nullptr, 0, n);
+  return hipGetLastError();
+}
+
+// x += alpha p with the last step's alpha = (r.z) / (p.q) from the partials:
+// the update the direction kernel would have made, for a CG that stops (or
+// replaces its residual) right after a step.
+__global__ __launch_bounds__(kCgThreads) void cg_x_update_kernel(double* __restrict__ x,
+                                                                 const double* __restrict__ p,
+                                                                 const double* __restrict__ part_rz,
+                                                                 const double* __restrict__ part_pq, int n_pq,
+                                                                 int64_t n) {
+  __shared__ double ws[kCgThreads / 64];
+  const double rz = cg_total(part_rz, ws);
+  const double alpha = rz / cg_total(part_pq, ws, n_pq);
+  const int64_t stride = (int64_t)kCgBlocks * kCgThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kCgThreads + threadIdx.x; i < n; i += stride) x[i] = x[i] + alpha * p[i];
+}
+
+hipError_t launch_cg_x_update(double* x, const double* p, const double* part_rz, const double* part_pq, int n_pq,
+                              int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cg_x_update_kernel, dim3(kCgBlocks), dim3(kCgThreads), 0, s, x, p, part_rz, part_pq, n_pq, n);
   return hipGetLastError();
 }
 
