@@ -1,5 +1,7 @@
 """GPU Newton-CG and adjoint solves vs the oracle's direct-solve versions,
 and the autograd design gradient vs central finite differences."""
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -265,3 +267,98 @@ def test_curved_q7_adjoint_gradient_c5():
     assert worst <= 1e-5
     del prob
     torch.cuda.empty_cache()
+
+
+def _pcg_iterate(K, b, dinv, m):
+    """x after m iterations of Jacobi-preconditioned CG on K x = b from x = 0,
+    in the textbook recurrence (Hestenes and Stiefel, 1952), FP64."""
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = dinv * r
+    p = z.copy()
+    rz = r @ z
+    for _ in range(m):
+        q = K @ p
+        a = rz / (p @ q)
+        x += a * p
+        r -= a * q
+        z = dinv * r
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x
+
+
+@pytest.mark.parametrize("max_cg,check_every", [(3, 10), (5, 2), (8, 1)])
+def test_one_newton_step_with_capped_cg(max_cg, check_every):
+    """One Newton step (max_newton = 1, called through the C ABI, which then
+    reports the Newton cap) from u0 = M u*/2: the step u1 - u0 must be
+    t du with t a power of two (the energy line search halves) and du the
+    Jacobi-preconditioned CG iterate of J(u0) du = -R(u0) (Eq. (2)) after
+    the reported number of iterations.  That number is max_cg, or a multiple
+    of check_every at which the residual fell below the forcing term 0.1
+    |R(u0)|: every CG step's alpha p must reach x, whether CG stops at the cap
+    or at a residual check."""
+    w = Workload("cap", 4, 3, 3, 3, 5, 3.0, 1e-2, 37, perturb=True, rho=True)
+    announce("capped CG Newton step", w, max_cg, check_every)
+    prob, ora, _ = setup(w)
+    u_star, _ = newton(ora, tol=1e-13)
+    u0 = ora.mask * (0.5 * u_star)
+    u = dev(u0)
+    o = feod.default_opts(max_newton=1, max_cg=max_cg, check_every=check_every, init_poisson=0)
+    rep = feod.feod.SolverReport()
+    L = feod.lib()
+    prob._sync_stream()
+    st = L.feod_newton_solve(prob._ctx, u.data_ptr(), ctypes.byref(o), ctypes.byref(rep))
+    assert st == feod.feod.FEOD_ENOCONV, L.feod_last_error(prob._ctx).decode()
+    rep = rep.as_dict()
+    iters = rep["cg_iters_total"]
+    print("CG iterations", iters, "report", rep)
+    assert rep["newton_iters"] == 1 and 1 <= iters <= max_cg
+    assert iters == max_cg or iters % check_every == 0
+    R = ora.residual(u0)
+    K = ora.jacobian(u0)
+    d = K.diagonal()
+    dinv = np.where(d > 0, 1.0 / np.where(d > 0, d, 1.0), 0.0)
+    du = _pcg_iterate(K, -R, dinv, iters)
+    if iters < max_cg:
+        assert np.linalg.norm(K @ du + R) <= 0.1 * np.linalg.norm(R) * (1 + 1e-9)
+    step = host(u) - u0
+    t_est = float(step @ du) / float(du @ du)
+    t = 2.0 ** round(np.log2(t_est))
+    assert abs(t_est - t) <= 1e-9 * t
+    assert relerr(step, t * du) <= 1e-9
+
+
+def test_cg_check_interval_and_cap_match_oracle():
+    """The Newton solution (Eq. (1)) and the adjoint gradient (the paragraph
+    after Eq. (3)) do not depend on how often CG reads its residual back or
+    on a cap on the CG iterations of the inexact Newton steps, in FP64 and
+    mixed precision; a capped adjoint CG that cannot converge is an error."""
+    w = Workload("cgopt", 4, 3, 3, 3, 5, 3.0, 1e-2, 37, perturb=True, rho=True)
+    announce("CG options", w)
+    prob, ora, _ = setup(w)
+    u_o, _ = newton(ora, tol=1e-13)
+    b = dev(ora.b)
+    lam_o, grad_o = adjoint(ora, u_o, ora.b)
+    for prec in ("fp64", "mixed"):
+        _, rep_d = prob.newton_solve(rtol=1e-12, prec=prec)
+        for kw in ({"check_every": 1}, {"check_every": 7}, {"max_cg": 6}):
+            u, rep = prob.newton_solve(rtol=1e-12, prec=prec, **kw)
+            print(prec, kw, "Newton", rep["newton_iters"], "CG", rep["cg_iters_total"])
+            assert rep["status"] == 0 and rep["res_final"] <= 1e-12 * rep["ref_norm"]
+            assert relerr(host(u), u_o) <= 1e-10
+            if "max_cg" in kw:
+                assert rep["cg_iters_total"] <= 6 * (rep["newton_iters"] + 1)
+                assert rep["newton_iters"] > rep_d["newton_iters"]
+        u = dev(u_o)
+        for ce in (1, 3):
+            grad, lam, rep = prob.adjoint_gradient(u, b, rtol=1e-13, prec=prec, check_every=ce)
+            print(prec, "adjoint check_every", ce, rep)
+            assert relerr(host(lam), lam_o) <= 1e-10
+            assert relerr(host(grad), grad_o) <= 1e-10
+            if prec == "mixed":
+                assert rep["refine_iters"] >= 1
+        with pytest.raises(feod.FeodError) as err:
+            prob.adjoint_gradient(u, b, rtol=1e-13, prec=prec, max_cg=2)
+        assert err.value.status == feod.feod.FEOD_ENOCONV
