@@ -362,3 +362,34 @@ def test_cg_check_interval_and_cap_match_oracle():
         with pytest.raises(feod.FeodError) as err:
             prob.adjoint_gradient(u, b, rtol=1e-13, prec=prec, max_cg=2)
         assert err.value.status == feod.feod.FEOD_ENOCONV
+
+
+def test_side_stream_results_equal_default_stream():
+    """Every call enqueues on torch's current stream: the residual, the
+    Jacobian action in both precisions, the Newton solve and the adjoint
+    gradient issued under a second stream (default priority) equal the
+    default stream's results bit for bit."""
+    w = Workload("stream", 5, 4, 3, 2, 3, 3.0, 1e-2, 38, perturb=True, rho=True)
+    announce("side stream", w)
+    prob, ora, inp = setup(w)
+    u, v, b = dev(inp["u"]), dev(inp["v"]), dev(ora.b)
+
+    def run():
+        r = prob.residual(u)
+        jv = prob.jacobian_apply(u, v)
+        jv32 = prob.jacobian_apply(u, v, prec="mixed")
+        us, _ = prob.newton_solve(rtol=1e-12)
+        g, lam, _ = prob.adjoint_gradient(us, b, rtol=1e-12)
+        return r, jv, jv32, us, g, lam
+
+    ref = run()
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream(device="cuda:0")
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        got = run()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    for name, a, c in zip(("residual", "jvp", "jvp mixed", "newton u", "grad", "lambda"), ref, got):
+        assert torch.equal(a, c), name
+    assert relerr(host(got[0]), ora.residual(inp["u"])) <= 1e-12
