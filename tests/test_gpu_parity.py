@@ -189,6 +189,36 @@ def test_lattice_and_explicit_maps_bitwise_equal(w):
         assert np.array_equal(a, b)
 
 
+@pytest.mark.parametrize("name", ["c2", "c4"])
+def test_full_size_lattice_and_explicit_maps_bitwise_equal(name):
+    """At 32^3 Q3 and 48^3 Q2 the computed G^T (FP64 tiles at k = 2, lattice
+    order at k = 3; FP32 element runs with wide stores at both) spans several
+    tiles of runs per lattice row and a ragged last one: its applies, and the
+    adjoint CG solves through the fused G^T + p.q, must equal the stored CSR
+    map's bit for bit, in FP64 and mixed precision."""
+    w = WORKLOADS[name]
+    announce("full-size map modes", name)
+    prob, _, inp = setup(w, oracle=False)
+    u, v = dev(inp["u"]), dev(inp["v"])
+    g_u = dev(np.random.default_rng(71).standard_normal(w.n_dofs))
+    outs = {}
+    for mode in ("lattice", "explicit"):
+        prob.set_map_mode(mode)
+        res = []
+        for prec in ("fp64", "mixed"):
+            r, jv = prob.residual_and_jvp(u, v, prec=prec)
+            res += [host(r), host(jv), host(prob.jacobian_apply(u, v, prec=prec))]
+            g, lam, rep = prob.adjoint_gradient(u, g_u, rtol=1e-8, prec=prec)
+            assert rep["status"] == 0, rep
+            res += [host(g), host(lam)]
+        outs[mode] = res
+    for i, (a, b) in enumerate(zip(outs["lattice"], outs["explicit"])):
+        assert np.array_equal(a, b), i
+    prob.set_map_mode("lattice")
+    del prob
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("w", [SMALL[0], SMALL[2], SMALL[3], SMALL[4], SMALL[5], SMALL[6], SMALL[8]],
                          ids=["c1", "q2-curved", "q3-p4", "q3-curved", "q4", "q7-curved", "q2-generic"])
 def test_jacobian_diagonal_matches_assembled_oracle(w):
