@@ -189,10 +189,11 @@ def test_lattice_and_explicit_maps_bitwise_equal(w):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("name", ["c2", "c4"])
+@pytest.mark.parametrize("name", ["c2", "c4", "c3"])
 def test_full_size_lattice_and_explicit_maps_bitwise_equal(name):
-    """At 32^3 Q3 and 48^3 Q2 the computed G^T (FP64 tiles at k = 2, lattice
-    order at k = 3; FP32 element runs with wide stores at both) spans several
+    """At 32^3 Q3, 48^3 Q2 and 64^3 Q4 the computed G^T (FP64 tiles at k = 2
+    and 4, lattice order at k = 3; FP32 element runs with wide stores at all
+    three) spans several
     tiles of runs per lattice row and a ragged last one: its applies, and the
     adjoint CG solves through the fused G^T + p.q, must equal the stored CSR
     map's bit for bit, in FP64 and mixed precision."""
