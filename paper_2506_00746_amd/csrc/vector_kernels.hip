@@ -252,6 +252,15 @@ __global__ __launch_bounds__(kVecThreads) void gather_t_tiles_kernel(LatticeDims
 // x-lines (contiguous in the E-vector) and each row's stores are contiguous.
 // Sums per DOF in ascending element order, absent candidates as +0 and a
 // final + 0: bitwise the explicit map's 0 + c_1 + c_2 + ...
+// Workgroup size of the run kernel per order: 512 threads at k = 4 (64^3
+// Q4: 78.9-79.3 against 82.9-83.0 us with 256), 256 otherwise (32^3 Q3: 8.2
+// against 8.5-8.6 us with 512; 48^3 Q2 the same either way).  The tile
+// kernel keeps 256 (64^3 Q4 FP64: 95 against 99 us with 512).
+template <int K>
+constexpr int run_threads() {
+  return K == 4 ? 512 : 256;
+}
+
 struct RunTiles {
   uint32_t th, tr, ngr, nplane, ntiles;  // rows and runs per tile, run groups per row group, tiles per plane, total
   FastDiv div_th, div_ngr, div_nplane;
@@ -303,14 +312,14 @@ __device__ __forceinline__ void run_sums(const LatticeDims& d, const TE* __restr
 }
 
 template <class TE, bool TWO, int K>
-__global__ __launch_bounds__(kVecThreads) void gather_t_runs_kernel(LatticeDims d, RunTiles g,
+__global__ __launch_bounds__(run_threads<K>()) void gather_t_runs_kernel(LatticeDims d, RunTiles g,
                                                                     const TE* __restrict__ Y0,
                                                                     const TE* __restrict__ Y1,
                                                                     const double* __restrict__ bm,
                                                                     double* __restrict__ out0,
                                                                     double* __restrict__ out1) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * (kVecThreads / 64) + (threadIdx.x >> 6);
+  const uint32_t t = (uint32_t)xcd_remap(blockIdx.x, gridDim.x) * (run_threads<K>() / 64) + (threadIdx.x >> 6);
   const uint32_t rr = fastdiv(lane, g.div_th), dy = lane - rr * g.th;
   const uint32_t kz = fastdiv(t, g.div_nplane), rem = t - kz * g.nplane;
   const uint32_t m = fastdiv(rem, g.div_ngr), gr = rem - m * g.ngr;
@@ -358,8 +367,9 @@ template <class TE, bool TWO, int K>
 static void launch_runs(const LatticeDims& d, const void* Y0, const void* Y1, const double* bm, double* out0,
                         double* out1, hipStream_t s) {
   const RunTiles g = make_run_tiles(d);
-  const int nb = (int)(((int64_t)g.ntiles + kVecThreads / 64 - 1) / (kVecThreads / 64));
-  hipLaunchKernelGGL((gather_t_runs_kernel<TE, TWO, K>), dim3(nb), dim3(kVecThreads), 0, s, d, g, (const TE*)Y0,
+  constexpr int W = run_threads<K>() / 64;  // wavefronts per workgroup
+  const int nb = (int)(((int64_t)g.ntiles + W - 1) / W);
+  hipLaunchKernelGGL((gather_t_runs_kernel<TE, TWO, K>), dim3(nb), dim3(run_threads<K>()), 0, s, d, g, (const TE*)Y0,
                      (const TE*)Y1, bm, out0, out1);
 }
 
@@ -377,7 +387,7 @@ static bool launch_runs_k(const LatticeDims& d, const void* Y0, const void* Y1, 
 hipError_t launch_gather_t_lattice(const LatticeDims& d, const void* Y0, const void* Y1, bool fp32,
                                    const double* bm, double* out0, double* out1, int64_t n, hipStream_t s) {
   // Per E-vector precision and order, the order measured fastest: runs for
-  // an FP32 E-vector at k = 2, 3, 4 (64^3 Q4 80-82 against 113-115 us in
+  // an FP32 E-vector at k = 2, 3, 4 (64^3 Q4 76-79 against 113-115 us in
   // lattice order, 32^3 Q3 8.5 against 9.3-9.5, 48^3 Q2 10.1 against
   // 10.6-10.8), tiles for FP64 at k = 2, 4 (runs: 127 us at 64^3 Q4), and
   // lattice order for the rest (runs at 16^3 Q7: 12.6-12.7 against
